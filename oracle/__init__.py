@@ -1,0 +1,167 @@
+"""CPU oracle for systematic MDS erasure coding over GF(2^w).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg are the only callers.  The accelerated library never imports
+this package, and this package never imports the library.
+
+Thin ctypes binding over ``pyrit_oracle.c`` (plain C, log/antilog tables).
+Blocks are numpy ``uint8`` arrays of ``w * S`` bytes: slice ``t`` of a block is
+``block[t*S:(t+1)*S]`` (the paper's "w chunks" of a block, Sec. III).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pyrit_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+ERRORS = {0: "ok", -1: "invalid argument", -2: "modulus not irreducible",
+          -3: "code too long for the field", -4: "singular matrix",
+          -5: "too many erasures", -6: "out of memory"}
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, no intrinsics)."""
+    cmd = ["gcc", "-O2", "-fopenmp", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
+           _SRC, "-o", _LIB_PATH + ".tmp"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, u32, i32, sz = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int, ctypes.c_size_t
+    lib.or_field_create.argtypes = [i32, u32, ctypes.POINTER(vp)]
+    lib.or_field_create.restype = i32
+    lib.or_field_free.argtypes = [vp]
+    lib.or_field_free.restype = None
+    lib.or_field_generator.argtypes = [vp]
+    lib.or_field_generator.restype = u32
+    lib.or_mul.argtypes = [vp, u32, u32]
+    lib.or_mul.restype = u32
+    lib.or_inv.argtypes = [vp, u32]
+    lib.or_inv.restype = u32
+    lib.or_mul_many.argtypes = [vp, vp, vp, vp, sz]
+    lib.or_mul_many.restype = None
+    lib.or_cauchy.argtypes = [vp, i32, i32, vp]
+    lib.or_cauchy.restype = i32
+    lib.or_invert.argtypes = [vp, i32, vp]
+    lib.or_invert.restype = i32
+    lib.or_encode.argtypes = [vp, i32, i32, vp, vp, vp, sz, sz, sz, i32]
+    lib.or_encode.restype = i32
+    lib.or_decode.argtypes = [vp, i32, i32, vp, vp, i32, vp, sz, sz, sz, i32]
+    lib.or_decode.restype = i32
+    lib.or_max_threads.argtypes = []
+    lib.or_max_threads.restype = i32
+    _lib = lib
+    return lib
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int):
+        super().__init__(f"oracle error {code}: {ERRORS.get(code, 'unknown')}")
+        self.code = code
+
+
+def _check(rc: int) -> None:
+    if rc != 0:
+        raise OracleError(rc)
+
+
+def max_threads() -> int:
+    return int(_load().or_max_threads())
+
+
+def _ptr_array(arrs):
+    t = (ctypes.c_void_p * len(arrs))()
+    for i, a in enumerate(arrs):
+        assert a.dtype == np.uint8 and a.flags["C_CONTIGUOUS"]
+        t[i] = a.ctypes.data
+    return t
+
+
+class Field:
+    """GF(2^w) = F_2[x]/(p) with log/antilog tables (Sec. II-A)."""
+
+    def __init__(self, w: int, p: int):
+        lib = _load()
+        h = ctypes.c_void_p()
+        _check(lib.or_field_create(w, p, ctypes.byref(h)))
+        self._h = h
+        self.w, self.p = w, p
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.or_field_free(h)
+            self._h = None
+
+    @property
+    def generator(self) -> int:
+        return int(_lib.or_field_generator(self._h))
+
+    def mul(self, a: int, b: int) -> int:
+        return int(_lib.or_mul(self._h, a, b))
+
+    def inv(self, a: int) -> int:
+        return int(_lib.or_inv(self._h, a))
+
+    def mul_many(self, a, b) -> np.ndarray:
+        a = np.ascontiguousarray(a, dtype=np.uint32)
+        b = np.ascontiguousarray(b, dtype=np.uint32)
+        out = np.empty_like(a)
+        _lib.or_mul_many(self._h, a.ctypes.data, b.ctypes.data, out.ctypes.data, a.size)
+        return out
+
+    def cauchy(self, k: int, m: int) -> np.ndarray:
+        C = np.zeros((m, k), dtype=np.uint16)
+        _check(_lib.or_cauchy(self._h, k, m, C.ctypes.data))
+        return C
+
+    def invert(self, A) -> np.ndarray:
+        A = np.array(A, dtype=np.uint16, order="C")
+        _check(_lib.or_invert(self._h, A.shape[0], A.ctypes.data))
+        return A
+
+    def encode(self, C, data, S: int, o0: int = 0, o1: int | None = None,
+               nthreads: int = 1, parity=None):
+        """Parity blocks for ``data`` (list of k blocks of w*S bytes)."""
+        C = np.ascontiguousarray(C, dtype=np.uint16)
+        m, k = C.shape
+        assert len(data) == k
+        if o1 is None:
+            o1 = S
+        if parity is None:
+            parity = [np.zeros(self.w * S, dtype=np.uint8) for _ in range(m)]
+        _check(_lib.or_encode(self._h, k, m, C.ctypes.data, _ptr_array(data),
+                              _ptr_array(parity), S, o0, o1, nthreads))
+        return parity
+
+    def decode(self, C, erased, blocks, S: int, o0: int = 0, o1: int | None = None,
+               nthreads: int = 1):
+        """Overwrite the erased entries of ``blocks`` (k+m blocks) in place."""
+        C = np.ascontiguousarray(C, dtype=np.uint16)
+        m, k = C.shape
+        assert len(blocks) == k + m
+        if o1 is None:
+            o1 = S
+        er = (ctypes.c_int * max(1, len(erased)))(*erased)
+        _check(_lib.or_decode(self._h, k, m, C.ctypes.data, er, len(erased),
+                              _ptr_array(blocks), S, o0, o1, nthreads))
+        return blocks

@@ -1,0 +1,332 @@
+"""Pins for the CPU oracle: every check compares it with something other than
+itself (a schoolbook multiply, brute force, the binary-matrix form of the same
+linear map, closed forms, the paper's printed values).  CPU only."""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1709_00178_amd import workloads as W
+from tests import gf_schoolbook as sb
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLD = json.load(open(os.path.join(HERE, "golden", "paper_examples.json")))
+
+FIELDS = [(4, 0x1F), (8, 0x139), (10, 0x7FF), (6, 0x49), (8, 0x11D), (8, 0x1D7)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _build_oracle():
+    oracle.build()
+
+
+@pytest.mark.parametrize("w,p", FIELDS)
+def test_table_multiply_matches_schoolbook_all_pairs(w, p):
+    f = oracle.Field(w, p)
+    q = 1 << w
+    a, b = np.meshgrid(np.arange(q), np.arange(q), indexing="ij")
+    got = f.mul_many(a.ravel(), b.ravel())
+    want = sb.mul(a.ravel(), b.ravel(), w, p)
+    assert np.array_equal(got.astype(np.int64), want)
+
+
+@pytest.mark.parametrize("w,p", FIELDS)
+def test_inverse_by_exhaustive_search(w, p):
+    f = oracle.Field(w, p)
+    inv = sb.inverse_table(w, p)
+    for a in range(1, 1 << w):
+        assert f.inv(a) == inv[a]
+
+
+def test_field_axioms_gf16_all_triples():
+    w, p = 4, 0x1F
+    f = oracle.Field(w, p)
+    q = 1 << w
+    T = np.array([[f.mul(a, b) for b in range(q)] for a in range(q)])
+    for a, b, c in itertools.product(range(q), repeat=3):
+        assert T[T[a, b], c] == T[a, T[b, c]]
+        assert T[a, b ^ c] == T[a, b] ^ T[a, c]
+        assert T[a, b] == T[b, a]
+    assert all(T[1, a] == a for a in range(q))
+    assert all(T[0, a] == 0 for a in range(q))
+
+
+@pytest.mark.parametrize("w,p", FIELDS)
+def test_generator_is_smallest_primitive(w, p):
+    f = oracle.Field(w, p)
+    g = f.generator
+    order = (1 << w) - 1
+
+    def ord_of(x):
+        v, o = x, 1
+        while v != 1:
+            v = int(sb.mul(v, x, w, p))
+            o += 1
+            if o > order:
+                return None
+        return o
+
+    assert ord_of(g) == order
+    for x in range(2, g):
+        assert ord_of(x) != order
+
+
+def test_generator_values_for_workload_fields():
+    # x itself is never primitive here: p divides x^n + 1 so x has order n.
+    assert oracle.Field(4, 0x1F).generator == 3
+    assert oracle.Field(8, 0x139).generator == 3
+    assert oracle.Field(10, 0x7FF).generator == 11
+
+
+@pytest.mark.parametrize("w,p", [(4, 0x11), (8, 0x101), (6, 0x7F), (4, 0x15)])
+def test_reducible_modulus_rejected(w, p):
+    assert not sb.is_irreducible(p)
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.Field(w, p)
+    assert e.value.code == -2
+
+
+def test_paper_aop_field_relations():
+    ex = GOLD["aop_embedding_inverse"]
+    f = oracle.Field(ex["w"], ex["p"])
+    # x^3 * x = x^4, which the paper reduces to 1 + x + x^2 + x^3
+    assert f.mul(8, 2) == ex["x_pow_mod_p"]["4"]
+    # x^5 = 1 in the field because p divides x^5 + 1
+    assert f.mul(ex["x_pow_mod_p"]["4"], 2) == 1
+
+
+def test_paper_esp_field_relations():
+    ex = GOLD["esp_embedding_inverse"]
+    f = oracle.Field(ex["w"], ex["p"])
+    x5 = 1 << 5
+    assert f.mul(x5, 2) == ex["x_pow_mod_p"]["6"]
+    assert f.mul(x5, 4) == ex["x_pow_mod_p"]["7"]
+    assert f.mul(x5, 8) == ex["x_pow_mod_p"]["8"]
+
+
+def test_cauchy_c0_values():
+    f = oracle.Field(4, 0x1F)
+    C = f.cauchy(4, 2)
+    inv = sb.inverse_table(4, 0x1F)
+    want = np.array([[inv[i ^ (2 + j)] for j in range(4)] for i in range(2)])
+    assert np.array_equal(C, want)
+    assert C.tolist() == [[15, 10, 8, 6], [10, 15, 6, 8]]
+
+
+@pytest.mark.parametrize("w,p,k,m", [(4, 0x1F, 4, 2), (8, 0x139, 10, 4), (10, 0x7FF, 16, 4),
+                                     (4, 0x1F, 12, 4), (6, 0x49, 8, 4)])
+def test_mds_every_square_submatrix_invertible(w, p, k, m):
+    """Every k x k selection of rows of [I; C] is invertible (Sec. II-B)."""
+    f = oracle.Field(w, p)
+    C = f.cauchy(k, m).astype(np.int64)
+    G = np.vstack([np.eye(k, dtype=np.int64), C])
+    sels = list(itertools.combinations(range(k + m), k))
+    mats = np.stack([G[list(s)] for s in sels])
+    assert sb.det_nonzero_all(mats, w, p).all()
+
+
+def test_cauchy_rejects_too_long_code():
+    f = oracle.Field(4, 0x1F)
+    with pytest.raises(oracle.OracleError) as e:
+        f.cauchy(13, 4)
+    assert e.value.code == -3
+
+
+def _rand_blocks(rng, k, w, S):
+    return [rng.integers(0, 256, size=w * S, dtype=np.uint8) for _ in range(k)]
+
+
+@pytest.mark.parametrize("w,p", FIELDS)
+def test_encode_matches_binary_matrix_form(w, p):
+    """The same linear map computed as XORs of whole slices (Sec. II-B: the
+    binary form of a coefficient; its ones are the XORs)."""
+    rng = np.random.Generator(np.random.PCG64(w * 1000 + p))
+    k, m, S = 5, 3, 128
+    G = rng.integers(0, 1 << w, size=(m, k)).astype(np.uint16)
+    data = _rand_blocks(rng, k, w, S)
+    f = oracle.Field(w, p)
+    got = f.encode(G, data, S)
+    want = sb.bitmatrix_encode(G, data, w, p, S)
+    for a, b in zip(got, want):
+        assert np.array_equal(a, b)
+
+
+def test_xor_parity_closed_form():
+    """An all-ones parity row gives the XOR of the data blocks (RAID-5)."""
+    w, p, k, S = 8, 0x139, 7, 256
+    rng = np.random.Generator(np.random.PCG64(5))
+    data = _rand_blocks(rng, k, w, S)
+    f = oracle.Field(w, p)
+    (par,) = f.encode(np.ones((1, k), dtype=np.uint16), data, S)
+    want = np.bitwise_xor.reduce(np.stack(data), axis=0)
+    assert np.array_equal(par, want)
+
+
+def test_unit_rows_copy_blocks():
+    w, p, k, S = 10, 0x7FF, 6, 64
+    rng = np.random.Generator(np.random.PCG64(6))
+    data = _rand_blocks(rng, k, w, S)
+    G = np.zeros((3, k), dtype=np.uint16)
+    G[0, 4] = G[1, 0] = G[2, 5] = 1
+    par = oracle.Field(w, p).encode(G, data, S)
+    assert np.array_equal(par[0], data[4])
+    assert np.array_equal(par[1], data[0])
+    assert np.array_equal(par[2], data[5])
+
+
+@pytest.mark.parametrize("w,p", [(4, 0x1F), (8, 0x139), (10, 0x7FF)])
+@pytest.mark.parametrize("s", [1, 3])
+def test_multiply_by_x_power_closed_form(w, p, s):
+    """u * x^s on bit slices: shift slice t to t+1, and fold the slice that
+    leaves degree w back through the low bits of p; repeated s times."""
+    S = 64
+    rng = np.random.Generator(np.random.PCG64(7 + s))
+    (d,) = _rand_blocks(rng, 1, w, S)
+    sl = [d[t * S:(t + 1) * S].copy() for t in range(w)]
+    for _ in range(s):
+        top = sl[w - 1]
+        sl = [np.zeros(S, dtype=np.uint8)] + sl[:w - 1]
+        for t in range(w):
+            if (p >> t) & 1:
+                sl[t] = sl[t] ^ top
+    want = np.concatenate(sl)
+    (got,) = oracle.Field(w, p).encode(np.array([[1 << s]], dtype=np.uint16), [d], S)
+    assert np.array_equal(got, want)
+
+
+def test_symbol_view_single_bit():
+    """Setting bit b of byte o of slice t sets coefficient t of symbol (o, b)."""
+    w, p, S = 8, 0x139, 64
+    f = oracle.Field(w, p)
+    for (t, o, b) in [(0, 0, 0), (7, 63, 7), (3, 17, 5)]:
+        d = np.zeros(w * S, dtype=np.uint8)
+        d[t * S + o] = 1 << b
+        u = 1 << t
+        for c in [1, 2, 0x53, 0xFF]:
+            (par,) = f.encode(np.array([[c]], dtype=np.uint16), [d], S)
+            prod = int(sb.mul(u, c, w, p))
+            want = np.zeros(w * S, dtype=np.uint8)
+            for tt in range(w):
+                if (prod >> tt) & 1:
+                    want[tt * S + o] = 1 << b
+            assert np.array_equal(par, want)
+
+
+def test_encode_is_linear():
+    w, p, k, m, S = 8, 0x139, 4, 3, 64
+    rng = np.random.Generator(np.random.PCG64(8))
+    f = oracle.Field(w, p)
+    C = f.cauchy(k, m)
+    a = _rand_blocks(rng, k, w, S)
+    b = _rand_blocks(rng, k, w, S)
+    pa, pb = f.encode(C, a, S), f.encode(C, b, S)
+    pab = f.encode(C, [x ^ y for x, y in zip(a, b)], S)
+    for x, y, z in zip(pa, pb, pab):
+        assert np.array_equal(x ^ y, z)
+
+
+def test_column_range_and_threads():
+    w, p, k, m, S = 8, 0x139, 4, 2, 4096
+    rng = np.random.Generator(np.random.PCG64(9))
+    f = oracle.Field(w, p)
+    C = f.cauchy(k, m)
+    data = _rand_blocks(rng, k, w, S)
+    full = f.encode(C, data, S, nthreads=1)
+    full4 = f.encode(C, data, S, nthreads=4)
+    for x, y in zip(full, full4):
+        assert np.array_equal(x, y)
+    part = f.encode(C, data, S, o0=100, o1=300,
+                    parity=[np.full(w * S, 0xAA, dtype=np.uint8) for _ in range(m)])
+    for x, y in zip(full, part):
+        for t in range(w):
+            sl = slice(t * S, (t + 1) * S)
+            assert np.array_equal(x[sl][100:300], y[sl][100:300])
+            assert (y[sl][:100] == 0xAA).all() and (y[sl][300:] == 0xAA).all()
+
+
+def test_invert_times_matrix_is_identity():
+    w, p, k = 8, 0x139, 10
+    f = oracle.Field(w, p)
+    C = f.cauchy(k, k).astype(np.int64)
+    Ai = f.invert(C).astype(np.int64)
+    mt = sb.mul_table(w, p)
+    prod = np.zeros((k, k), dtype=np.int64)
+    for i in range(k):
+        for j in range(k):
+            acc = 0
+            for r in range(k):
+                acc ^= mt[C[i, r], Ai[r, j]]
+            prod[i, j] = acc
+    assert np.array_equal(prod, np.eye(k, dtype=np.int64))
+
+
+def _roundtrip(w, p, k, m, S, patterns, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    f = oracle.Field(w, p)
+    C = f.cauchy(k, m)
+    data = _rand_blocks(rng, k, w, S)
+    parity = f.encode(C, data, S)
+    code = data + parity
+    for er in patterns:
+        blocks = [b.copy() for b in code]
+        for e in er:
+            blocks[e][:] = 0x5A
+        f.decode(C, list(er), blocks, S)
+        for i in range(k + m):
+            assert np.array_equal(blocks[i], code[i]), (er, i)
+
+
+def test_decode_every_pattern_c0():
+    st = W.c0()
+    pats = [(e,) for e in range(6)] + W.c0_erasure_patterns()
+    _roundtrip(st.w, st.p, st.k, st.m, 256, pats, 10)
+
+
+def test_decode_every_four_erasure_pattern_c1_shape():
+    st = W.c1()
+    pats = list(itertools.combinations(range(st.k + st.m), 4))
+    assert len(pats) == 1001
+    _roundtrip(st.w, st.p, st.k, st.m, 64, pats, 11)
+
+
+def test_decode_patterns_c2_shape_sampled():
+    st = W.c2(1)[0]
+    rng = np.random.Generator(np.random.PCG64(12))
+    pats = [tuple(sorted(rng.choice(20, size=int(rng.integers(1, 5)), replace=False)))
+            for _ in range(60)]
+    _roundtrip(st.w, st.p, st.k, st.m, 64, pats, 12)
+
+
+def test_decode_errors():
+    w, p, k, m, S = 4, 0x1F, 4, 2, 64
+    f = oracle.Field(w, p)
+    C = f.cauchy(k, m)
+    blocks = [np.zeros(w * S, dtype=np.uint8) for _ in range(k + m)]
+    with pytest.raises(oracle.OracleError) as e:
+        f.decode(C, [0, 1, 2], blocks, S)
+    assert e.value.code == -5
+    bad = np.array([[1, 1, 1, 1], [1, 1, 1, 1]], dtype=np.uint16)
+    with pytest.raises(oracle.OracleError) as e:
+        f.decode(bad, [0, 1], blocks, S)
+    assert e.value.code == -4
+
+
+def test_oracle_on_workload_generator_bytes():
+    """The generator's bytes are what the oracle codes: a round trip on the
+    small workload with its seeded blocks."""
+    st = W.c0()
+    f = oracle.Field(st.w, st.p)
+    C = f.cauchy(st.k, st.m)
+    data = W.host_blocks(st)
+    par = f.encode(C, data, st.S, nthreads=4)
+    code = data + par
+    for er in W.c0_erasure_patterns():
+        blocks = [b.copy() for b in code]
+        for e in er:
+            blocks[e][:] = 0
+        f.decode(C, list(er), blocks, st.S, nthreads=4)
+        for a, b in zip(blocks, code):
+            assert np.array_equal(a, b)
