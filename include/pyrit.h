@@ -1,0 +1,171 @@
+/*
+ * pyrit.h: C ABI of the MI355X (gfx950) erasure-coding library.
+ *
+ * Systematic MDS erasure codes over GF(2^w) = F_2[x]/(p(x)), computed in the
+ * polynomial ring R_{2,n} = F_2[x]/(x^n + 1) with n odd and p dividing
+ * x^n + 1, after Detchart & Lacan, "Improving the coding speed of erasure
+ * codes with polynomial ring transforms":
+ *   - each generator coefficient u is replaced by its sparsest ring
+ *     representative c (c = u mod p, fewest nonzero coefficients; the
+ *     "sparse transform" of Sec. II-B);
+ *   - each data block is embedded in the ring by padding its w slices with
+ *     n - w zero slices (the embedding transform of Sec. II-C.2 / II-D.2);
+ *   - multiplying by x^s rotates slice indices by s modulo n, so a product is
+ *     an XOR of rotated slices, and the n ring slices of each output are
+ *     reduced modulo p back to w field slices (inverse embedding, Prop. 2).
+ *
+ * Data layout.  A block is w contiguous slices of S bytes ("slice_bytes").
+ * Slice t holds coefficient t of every symbol: symbol (o, b), for byte offset
+ * o < S and bit b < 8, is sum_t bit b of byte o of slice t, times x^t.  S must
+ * be a positive multiple of 64, every block pointer 16-byte aligned, and
+ * w * S < 2^31.
+ *
+ * Integers that encode polynomials over GF(2) use bit i for the coefficient
+ * of x^i (p includes its x^w term: x^8+x^5+x^4+x^3+1 is 0x139).
+ *
+ * Conventions.  Every entry point returns PYRIT_OK (0) or a negative
+ * PYRIT_E* code; no C++ exception crosses this boundary.  Pointer arrays
+ * (data[], parity[], blocks[]) are host arrays of device pointers; the
+ * library copies them before returning.  Device work is enqueued on the
+ * caller's stream (a hipStream_t passed as void*, NULL = the null stream)
+ * and runs asynchronously: device faults surface at the caller's next
+ * synchronisation.  The caller owns every device buffer and stream.  Plans
+ * are immutable after creation (their decode cache is internally locked), so
+ * several streams may use one plan at once.
+ */
+#ifndef PYRIT_H
+#define PYRIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  PYRIT_OK = 0,
+  PYRIT_EINVAL = -1,       /* bad argument: size, count, NULL pointer */
+  PYRIT_ENOTIRRED = -2,    /* p is not irreducible of degree w */
+  PYRIT_ENOTDIV = -3,      /* n even, or p does not divide x^n + 1 */
+  PYRIT_ETOOLONG = -4,     /* k + m exceeds 2^w (Cauchy code length limit) */
+  PYRIT_ERANGE = -5,       /* a generator coefficient is >= 2^w */
+  PYRIT_ETOOMANY = -6,     /* more erasures than parity blocks */
+  PYRIT_ESINGULAR = -7,    /* surviving rows of [I; G] are not invertible */
+  PYRIT_EALIGN = -8,       /* slice size or pointer alignment */
+  PYRIT_EUNSUPPORTED = -9, /* no device kernel for this (w, n, p) ring */
+  PYRIT_EHIP = -10,        /* a HIP runtime call failed */
+  PYRIT_ENOMEM = -11,      /* host or device allocation failed */
+  PYRIT_EBUSY = -12        /* resource cap reached (serving admission) */
+};
+
+#define PYRIT_KMAX 64      /* maximum data blocks per stripe */
+#define PYRIT_MMAX 64      /* maximum parity blocks per stripe */
+#define PYRIT_SMAX_TOTAL 0x7fffffffu /* w * S must stay below this */
+
+/* Text for an error code (static storage). */
+const char *pyrit_strerror(int code);
+
+/* Library version string, e.g. "pyrit-mi355x 0.1". */
+const char *pyrit_version(void);
+
+/* ------------------------------------------------------------------ algebra
+ * Host-side helpers; no device work, usable without a GPU.
+ */
+
+/* Check a field/ring pair (Sec. II-A): 1 <= w <= 16, deg p = w, p
+ * irreducible, w < n <= 24, n odd, p divides x^n + 1.  Returns PYRIT_OK,
+ * PYRIT_EINVAL, PYRIT_ENOTIRRED or PYRIT_ENOTDIV. */
+int pyrit_ring_check(int w, int n, uint32_t p);
+
+/* Whether a device kernel exists for this ring (1) or not (0). */
+int pyrit_ring_supported(int w, int n, uint32_t p);
+
+/* Sparse transform of one field element (Sec. II-B): among the 2^(n-w) ring
+ * elements c with c mod p == u (deg c < n), return in *c one of least
+ * Hamming weight, the numerically smallest on ties. */
+int pyrit_lift(int w, int n, uint32_t p, uint32_t u, uint32_t *c);
+
+/* Inverse embedding (Prop. 2, Sec. II-C.2): *u = c mod p for a ring element
+ * c of degree < n. */
+int pyrit_ring_reduce(int w, int n, uint32_t p, uint32_t c, uint32_t *u);
+
+/* Product in R_{2,n} = F_2[x]/(x^n + 1): the cyclic convolution of a and b. */
+int pyrit_ring_mul(int n, uint32_t a, uint32_t b, uint32_t *c);
+
+/* Product in GF(2^w) = F_2[x]/(p). */
+int pyrit_gf_mul(int w, uint32_t p, uint32_t a, uint32_t b, uint32_t *c);
+
+/* Plain Cauchy parity matrix (Sec. III uses Cauchy-type MDS generators):
+ * G[i*k + j] = 1 / (i + (m + j)) in GF(2^w), i < m, j < k.  Requires
+ * k + m <= 2^w.  G is a host array of m*k entries. */
+int pyrit_cauchy(int w, uint32_t p, int k, int m, uint16_t *G);
+
+/* -------------------------------------------------------------------- plans */
+typedef struct pyrit_plan pyrit_plan;
+
+/* Build the lifted XOR schedule of the systematic code [I_k; G] (G is the
+ * m x k row-major parity part, host memory, copied).  Validates the ring
+ * (pyrit_ring_check), 1 <= k <= PYRIT_KMAX, 1 <= m <= PYRIT_MMAX,
+ * k + m <= 2^w and every G entry < 2^w.  A plan for a ring without a device
+ * kernel is still created (host queries work); device calls on it return
+ * PYRIT_EUNSUPPORTED.  *out receives the plan. */
+int pyrit_plan_create(int w, int n, uint32_t p, int k, int m, const uint16_t *G,
+                      pyrit_plan **out);
+
+/* Release a plan and its device copies.  NULL is ignored.  The caller must
+ * ensure no stream still runs work that uses the plan. */
+void pyrit_plan_destroy(pyrit_plan *plan);
+
+/* Code parameters of a plan (any pointer may be NULL). */
+int pyrit_plan_params(const pyrit_plan *plan, int *w, int *n, uint32_t *p, int *k, int *m);
+
+/* The m*k lifted ring elements (row-major, host array of m*k uint32). */
+int pyrit_plan_lifted(const pyrit_plan *plan, uint32_t *C);
+
+/* Total Hamming weight of the lifted matrix: the number of rotated-slice
+ * XOR terms per output column ("number of ones", Sec. II-B). */
+int pyrit_plan_weight(const pyrit_plan *plan, int *weight);
+
+/* Decoding matrix for an erasure pattern (Sec. IV-C): survivors are the first
+ * k block ids in 0..k+m-1 that are not erased; D (n_erased x k, row-major,
+ * host) maps the survivors to the erased blocks in the listed order:
+ * D = G_E * A^{-1} with A the survivors' rows of [I; G] and G_E the erased
+ * rows.  survivors (k ints) and D may be NULL. */
+int pyrit_decode_matrix(const pyrit_plan *plan, const int *erased, int n_erased,
+                        int *survivors, uint16_t *D);
+
+/* ------------------------------------------------------------- device calls */
+
+/* Encode: parity[i] = sum_j G[i][j] * data[j] for i < m, computed as
+ * rotated-slice XORs in R_{2,n} and reduced mod p.  data: k device pointers,
+ * parity: m device pointers (host arrays), each block w * slice_bytes bytes.
+ * Outputs must not alias inputs. */
+int pyrit_encode(const pyrit_plan *plan, const uint8_t *const *data, uint8_t *const *parity,
+                 size_t slice_bytes, void *stream);
+
+/* Decode: blocks holds k + m device pointers (data then parity).  Entries
+ * listed in erased[] (distinct ids, n_erased <= m) are outputs; the first k
+ * non-erased entries are read.  The decoding matrix is built on the host
+ * (cached per pattern) and the encode kernel runs with it. */
+int pyrit_decode(const pyrit_plan *plan, const int *erased, int n_erased,
+                 uint8_t *const *blocks, size_t slice_bytes, void *stream);
+
+/* Same as pyrit_encode with explicit lanes' column width (4, 8 or 16 bytes
+ * per lane; 0 = the library's choice).  Used by the tuner and the tests. */
+int pyrit_encode_vec(const pyrit_plan *plan, const uint8_t *const *data, uint8_t *const *parity,
+                     size_t slice_bytes, int vec_bytes, void *stream);
+
+/* Fill nbytes of device memory with the seeded SplitMix64 stream (word q of
+ * the buffer is mix64(key + (q+1) * 0x9E3779B97F4A7C15), little endian) for
+ * bytes < nrandom, zero beyond.  nbytes must be a multiple of 8. */
+int pyrit_fill_random(uint8_t *dst, size_t nbytes, size_t nrandom, uint64_t key, void *stream);
+
+/* Device-to-device copy with the library's streaming copy kernel (16 bytes
+ * per lane); nbytes a multiple of 16.  A bandwidth reference. */
+int pyrit_copy(uint8_t *dst, const uint8_t *src, size_t nbytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PYRIT_H */

@@ -1,0 +1,185 @@
+"""PYRIT on MI355X: systematic MDS erasure coding over GF(2^w) computed as
+rotated-slice XORs in the ring F_2[x]/(x^n + 1) (Detchart & Lacan).
+
+Python binding over the C ABI in ``include/pyrit.h``.  Every coding step runs
+in the library's HIP kernels; torch is used only to hand over device pointers
+and the current stream.  Block buffers are uint8 device tensors of w * S
+bytes (w slices of S bytes).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from ._lib import lib
+
+__all__ = ["PyritError", "Plan", "ring_check", "ring_supported", "lift", "ring_reduce",
+           "ring_mul", "gf_mul", "cauchy", "fill_random", "copy", "version"]
+
+PYRIT_OK = 0
+
+
+class PyritError(RuntimeError):
+    def __init__(self, code: int):
+        msg = lib().pyrit_strerror(code).decode()
+        super().__init__(f"pyrit error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc: int) -> None:
+    if rc != PYRIT_OK:
+        raise PyritError(rc)
+
+
+def version() -> str:
+    return lib().pyrit_version().decode()
+
+
+def ring_check(w: int, n: int, p: int) -> int:
+    """0 when (w, n, p) is a valid field/ring pair, else the error code."""
+    return int(lib().pyrit_ring_check(w, n, p))
+
+
+def ring_supported(w: int, n: int, p: int) -> bool:
+    return bool(lib().pyrit_ring_supported(w, n, p))
+
+
+def lift(w: int, n: int, p: int, u: int) -> int:
+    c = ctypes.c_uint32()
+    _check(lib().pyrit_lift(w, n, p, u, ctypes.byref(c)))
+    return c.value
+
+
+def ring_reduce(w: int, n: int, p: int, c: int) -> int:
+    u = ctypes.c_uint32()
+    _check(lib().pyrit_ring_reduce(w, n, p, c, ctypes.byref(u)))
+    return u.value
+
+
+def ring_mul(n: int, a: int, b: int) -> int:
+    c = ctypes.c_uint32()
+    _check(lib().pyrit_ring_mul(n, a, b, ctypes.byref(c)))
+    return c.value
+
+
+def gf_mul(w: int, p: int, a: int, b: int) -> int:
+    c = ctypes.c_uint32()
+    _check(lib().pyrit_gf_mul(w, p, a, b, ctypes.byref(c)))
+    return c.value
+
+
+def cauchy(w: int, p: int, k: int, m: int) -> np.ndarray:
+    G = np.zeros((m, k), dtype=np.uint16)
+    _check(lib().pyrit_cauchy(w, p, k, m, G.ctypes.data))
+    return G
+
+
+def _dev_ptr(x) -> int:
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        if not x.is_cuda:
+            raise ValueError("block buffers must be device tensors")
+        return int(x.data_ptr())
+    raise TypeError(f"expected a device tensor or a pointer, got {type(x)}")
+
+
+def _stream_handle(stream) -> int | None:
+    if stream is None:
+        import torch
+        return int(torch.cuda.current_stream().cuda_stream) or None
+    if isinstance(stream, int):
+        return stream or None
+    return int(stream.cuda_stream) or None
+
+
+def _ptr_array(xs):
+    arr = (ctypes.c_void_p * max(1, len(xs)))()
+    for i, x in enumerate(xs):
+        arr[i] = _dev_ptr(x) if x is not None else None
+    return arr
+
+
+class Plan:
+    """A code [I_k; G] over GF(2^w) = F_2[x]/(p), lifted into R_{2,n}.
+
+    ``G`` (m x k) defaults to the plain Cauchy matrix 1 / (i + m + j).
+    """
+
+    def __init__(self, w: int, n: int, p: int, k: int, m: int, G=None):
+        if G is None:
+            G = cauchy(w, p, k, m)
+        G = np.ascontiguousarray(G, dtype=np.uint16)
+        if G.shape != (m, k):
+            raise ValueError(f"G must be {m}x{k}")
+        h = ctypes.c_void_p()
+        _check(lib().pyrit_plan_create(w, n, p, k, m, G.ctypes.data, ctypes.byref(h)))
+        self._h = h
+        self.w, self.n, self.p, self.k, self.m = w, n, p, k, m
+        self.G = G.copy()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pyrit_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self) -> int:
+        return self._h.value
+
+    @property
+    def lifted(self) -> np.ndarray:
+        C = np.zeros((self.m, self.k), dtype=np.uint32)
+        _check(lib().pyrit_plan_lifted(self._h, C.ctypes.data))
+        return C
+
+    @property
+    def weight(self) -> int:
+        wt = ctypes.c_int()
+        _check(lib().pyrit_plan_weight(self._h, ctypes.byref(wt)))
+        return wt.value
+
+    def decode_matrix(self, erased):
+        er = (ctypes.c_int * max(1, len(erased)))(*erased)
+        surv = np.zeros(self.k, dtype=np.int32)
+        D = np.zeros((len(erased), self.k), dtype=np.uint16)
+        _check(lib().pyrit_decode_matrix(self._h, er, len(erased), surv.ctypes.data,
+                                         D.ctypes.data))
+        return surv, D
+
+    def encode(self, data, parity, S: int, stream=None, vec_bytes: int = 0) -> None:
+        if len(data) != self.k or len(parity) != self.m:
+            raise ValueError("need k data and m parity buffers")
+        _check(lib().pyrit_encode_vec(self._h, _ptr_array(data), _ptr_array(parity), S,
+                                      vec_bytes, _stream_handle(stream)))
+
+    def decode(self, erased, blocks, S: int, stream=None) -> None:
+        if len(blocks) != self.k + self.m:
+            raise ValueError("need k + m block buffers")
+        er = (ctypes.c_int * max(1, len(erased)))(*erased)
+        _check(lib().pyrit_decode(self._h, er, len(erased), _ptr_array(blocks), S,
+                                  _stream_handle(stream)))
+
+
+def fill_random(buf, key: int, nrandom: int | None = None, nbytes: int | None = None,
+                stream=None) -> None:
+    """Fill a device buffer with the seeded SplitMix64 byte stream."""
+    if nbytes is None:
+        nbytes = buf.numel() * buf.element_size()
+    if nrandom is None:
+        nrandom = nbytes
+    _check(lib().pyrit_fill_random(_dev_ptr(buf), nbytes, nrandom, key & ((1 << 64) - 1),
+                                   _stream_handle(stream)))
+
+
+def copy(dst, src, nbytes: int | None = None, stream=None) -> None:
+    if nbytes is None:
+        nbytes = src.numel() * src.element_size()
+    _check(lib().pyrit_copy(_dev_ptr(dst), _dev_ptr(src), nbytes, _stream_handle(stream)))

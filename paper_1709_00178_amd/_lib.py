@@ -1,0 +1,61 @@
+"""ctypes loader for libpyrit.so (argument marshalling only).
+
+The library must have been built in-tree (``python -m paper_1709_00178_amd.build``
+or ``__graft_entry__.build()``).  There is no fallback: a missing library is an
+error.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpyrit.so")
+
+_lib = None
+
+c_int, c_u32, c_u64, c_size, c_vp = (ctypes.c_int, ctypes.c_uint32, ctypes.c_uint64,
+                                    ctypes.c_size_t, ctypes.c_void_p)
+P = ctypes.POINTER
+
+# name -> (restype, argtypes); mirrors include/pyrit.h
+SIGNATURES = {
+    "pyrit_strerror": (ctypes.c_char_p, [c_int]),
+    "pyrit_version": (ctypes.c_char_p, []),
+    "pyrit_ring_check": (c_int, [c_int, c_int, c_u32]),
+    "pyrit_ring_supported": (c_int, [c_int, c_int, c_u32]),
+    "pyrit_lift": (c_int, [c_int, c_int, c_u32, c_u32, P(c_u32)]),
+    "pyrit_ring_reduce": (c_int, [c_int, c_int, c_u32, c_u32, P(c_u32)]),
+    "pyrit_ring_mul": (c_int, [c_int, c_u32, c_u32, P(c_u32)]),
+    "pyrit_gf_mul": (c_int, [c_int, c_u32, c_u32, c_u32, P(c_u32)]),
+    "pyrit_cauchy": (c_int, [c_int, c_u32, c_int, c_int, c_vp]),
+    "pyrit_plan_create": (c_int, [c_int, c_int, c_u32, c_int, c_int, c_vp, P(c_vp)]),
+    "pyrit_plan_destroy": (None, [c_vp]),
+    "pyrit_plan_params": (c_int, [c_vp, P(c_int), P(c_int), P(c_u32), P(c_int), P(c_int)]),
+    "pyrit_plan_lifted": (c_int, [c_vp, c_vp]),
+    "pyrit_plan_weight": (c_int, [c_vp, P(c_int)]),
+    "pyrit_decode_matrix": (c_int, [c_vp, c_vp, c_int, c_vp, c_vp]),
+    "pyrit_encode": (c_int, [c_vp, c_vp, c_vp, c_size, c_vp]),
+    "pyrit_encode_vec": (c_int, [c_vp, c_vp, c_vp, c_size, c_int, c_vp]),
+    "pyrit_decode": (c_int, [c_vp, c_vp, c_int, c_vp, c_size, c_vp]),
+    "pyrit_fill_random": (c_int, [c_vp, c_size, c_size, c_u64, c_vp]),
+    "pyrit_copy": (c_int, [c_vp, c_vp, c_size, c_vp]),
+}
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_1709_00178_amd.build` "
+            "(there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L

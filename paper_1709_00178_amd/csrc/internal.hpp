@@ -1,0 +1,80 @@
+// Internal declarations shared by the host plan, the launchers and the C ABI.
+#pragma once
+#include <array>
+#include <cstdint>
+#include <memory>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/pyrit.h"
+
+namespace pyrit {
+
+// Outputs computed by one kernel pass: the accumulators of every output live
+// in registers, so a pass covers at most this many output blocks.
+constexpr int kMaxOut = 4;
+
+// Rings with a device kernel.  The kernels are templates on (w, n, p), so the
+// reduction modulo p and every rotation index are compile-time constants.
+struct RingDesc {
+  int w, n;
+  uint32_t p;
+};
+constexpr int kNumRings = 5;
+constexpr RingDesc kRings[kNumRings] = {
+    {4, 5, 0x1Fu},     // all-one polynomial of degree 4 (Sec. II-C)
+    {8, 17, 0x139u},   // x^8+x^5+x^4+x^3+1, divides x^17+1
+    {8, 17, 0x1D7u},   // x^8+x^7+x^6+x^4+x^2+x+1, the other factor
+    {10, 11, 0x7FFu},  // all-one polynomial of degree 10
+    {6, 9, 0x49u},     // equally spaced x^6+x^3+1 (Sec. II-D)
+};
+int ring_id(int w, int n, uint32_t p);  // -1 when no kernel exists
+
+// Arguments of one coding pass: outputs out[r] (r < nout) are
+// sum_j lift[j][r] (*) in[j] in the ring, reduced mod p.
+struct PassArgs {
+  const uint8_t *in[PYRIT_KMAX];
+  uint8_t *out[kMaxOut];
+  uint32_t lift[PYRIT_KMAX][kMaxOut];
+  uint32_t k;
+  uint32_t S;
+};
+
+// Lanes' column width in bytes used when the caller does not choose.
+int default_vec_bytes(int ring, int nout);
+
+// Enqueue one pass (nout <= kMaxOut outputs) of the plain kernel.
+int launch_pass(int ring, int nout, int vec_bytes, const PassArgs &a, void *stream);
+
+struct DecodeEntry {
+  std::vector<int> surv;      // k survivor block ids
+  std::vector<int> outs;      // erased block ids, ascending
+  std::vector<uint16_t> D;    // outs.size() x k decoding matrix
+  std::vector<uint32_t> L;    // lifted D
+  int weight = 0;
+};
+
+// Lifted representative of every field element of a ring (size 2^w).
+const std::vector<uint32_t> &lift_table(int w, int n, uint32_t p);
+
+}  // namespace pyrit
+
+struct pyrit_plan {
+  int w = 0, n = 0;
+  uint32_t p = 0;
+  int k = 0, m = 0;
+  int ring = -1;
+  std::vector<uint16_t> G;  // m x k
+  std::vector<uint32_t> L;  // m x k lifted
+  int weight = 0;
+  mutable std::mutex mu;
+  mutable std::unordered_map<std::string, std::shared_ptr<const pyrit::DecodeEntry>> dcache;
+};
+
+namespace pyrit {
+// Decoding matrix for a pattern (cached on the plan).
+int decode_entry(const pyrit_plan *plan, const int *erased, int n_erased,
+                 std::shared_ptr<const DecodeEntry> *out);
+int check_slices(int w, size_t S);
+}  // namespace pyrit

@@ -1,0 +1,44 @@
+// Plain per-stripe kernel: one launch codes one pass (up to kMaxOut outputs)
+// of one stripe; lane i of block b owns column (b*256 + i) * 4V.
+#pragma once
+#include "ring_kernels.hpp"
+
+namespace pyrit {
+
+template <int RING, int MO, int V>
+__global__ __launch_bounds__(256) void plain_pass_kernel(const PassArgs a) {
+  constexpr RingDesc R = kRings[RING];
+  const uint32_t col = (blockIdx.x * 256u + threadIdx.x) * (4u * V);
+  dev::code_column<R.w, R.n, R.p, MO, V>(dev::KernargSrc{a}, col, col < a.S);
+}
+
+template <int RING, int MO, int V>
+static int launch_plain(const PassArgs &a, hipStream_t st) {
+  const uint32_t per_block = 256u * 4u * V;
+  const uint32_t blocks = (a.S + per_block - 1) / per_block;
+  hipLaunchKernelGGL((plain_pass_kernel<RING, MO, V>), dim3(blocks), dim3(256), 0, st, a);
+  return hipGetLastError() == hipSuccess ? PYRIT_OK : PYRIT_EHIP;
+}
+
+template <int RING, int MO>
+static int launch_plain_v(int vec_bytes, const PassArgs &a, hipStream_t st) {
+  switch (vec_bytes) {
+    case 4: return launch_plain<RING, MO, 1>(a, st);
+    case 8: return launch_plain<RING, MO, 2>(a, st);
+    case 16: return launch_plain<RING, MO, 4>(a, st);
+    default: return PYRIT_EINVAL;
+  }
+}
+
+template <int RING>
+int launch_plain_ring(int nout, int vec_bytes, const PassArgs &a, hipStream_t st) {
+  switch (nout) {
+    case 1: return launch_plain_v<RING, 1>(vec_bytes, a, st);
+    case 2: return launch_plain_v<RING, 2>(vec_bytes, a, st);
+    case 3: return launch_plain_v<RING, 3>(vec_bytes, a, st);
+    case 4: return launch_plain_v<RING, 4>(vec_bytes, a, st);
+    default: return PYRIT_EINVAL;
+  }
+}
+
+}  // namespace pyrit

@@ -1,0 +1,160 @@
+// Device side of one coding pass, for gfx950 (CDNA4, wave64).
+//
+// Each lane owns a column of 4*V bytes (V dwords) at byte offset `col` of
+// every slice.  For one output block r the lane keeps the n ring slices of
+// its column in registers (acc[r][0..n-1]).  Input block j contributes, for
+// every exponent s set in the lifted coefficient c[r][j] (Sec. II-B), its w
+// slices rotated by s: acc[r][(t + s) mod n] ^= slice t (multiplying by x^s
+// in R_{2,n}).  The embedding transform pads a block with n - w zero slices
+// (Sec. II-C.2), so those slices are never loaded.  After the last input,
+// ring slices w..n-1 are folded into the field slices through x^i mod p
+// (inverse embedding, Prop. 2) and the w field slices are stored.
+//
+// The set bits of a lifted coefficient are wave-uniform (scalar registers),
+// so each rotation is a scalar branch around an unrolled body whose
+// accumulator indices are compile-time constants: the accumulators never
+// leave registers and no schedule is read per XOR (the GPU form of the
+// paper's unrolled, schedule-free XOR code of Sec. III).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.hpp"
+
+namespace pyrit {
+namespace dev {
+
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <int V> struct Vec;
+template <> struct Vec<1> { typedef uint32_t T; };
+template <> struct Vec<2> { typedef u32x2 T; };
+template <> struct Vec<4> { typedef u32x4 T; };
+
+// Raw-buffer descriptor word 3 for gfx9-family parts (32-bit data format).
+constexpr int kBufDword3 = 0x00020000;
+// Cache policy bits of buffer instructions on gfx94x/gfx950: bit 1 = NT.
+constexpr int kLoadPolicy = 0;
+constexpr int kStorePolicy = 2;
+
+// x^i mod p for p of degree w, as a compile-time constant.
+constexpr uint32_t xpow_mod(int i, uint32_t p, int w) {
+  uint32_t v = 1;
+  for (int e = 0; e < i; ++e) {
+    v <<= 1;
+    if (v >> w & 1u) v ^= p;
+  }
+  return v;
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t block_rsrc(const void *base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
+                                           kBufDword3);
+}
+
+template <int V>
+__device__ __forceinline__ typename Vec<V>::T bload(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                                    uint32_t soff) {
+  if constexpr (V == 1)
+    return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, kLoadPolicy);
+  else if constexpr (V == 2)
+    return __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, kLoadPolicy);
+  else
+    return __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, kLoadPolicy);
+}
+
+template <int V>
+__device__ __forceinline__ void bstore(typename Vec<V>::T x, __amdgpu_buffer_rsrc_t r,
+                                       uint32_t voff, uint32_t soff) {
+  if constexpr (V == 1)
+    __builtin_amdgcn_raw_buffer_store_b32(x, r, voff, soff, kStorePolicy);
+  else if constexpr (V == 2)
+    __builtin_amdgcn_raw_buffer_store_b64(x, r, voff, soff, kStorePolicy);
+  else
+    __builtin_amdgcn_raw_buffer_store_b128(x, r, voff, soff, kStorePolicy);
+}
+
+// acc[(t + s) mod N] ^= d[t] for t < W and every s >= S0 set in c.
+template <int W, int N, int S0, typename T>
+__device__ __forceinline__ void rot_acc(T (&acc)[N], const T (&d)[W], uint32_t c) {
+  if constexpr (S0 < N) {
+    if (c & (1u << S0)) {
+#pragma unroll
+      for (int t = 0; t < W; ++t) acc[(t + S0) % N] ^= d[t];
+    }
+    rot_acc<W, N, S0 + 1, T>(acc, d, c);
+  }
+}
+
+// Fold ring slices W..N-1 into the field slices: slice i adds itself to
+// every field slice b with bit b of x^i mod p set.
+template <int W, int N, uint32_t P, typename T>
+__device__ __forceinline__ void reduce_mod_p(T (&acc)[N]) {
+#pragma unroll
+  for (int i = W; i < N; ++i) {
+    const uint32_t red = xpow_mod(i, P, W);
+#pragma unroll
+    for (int b = 0; b < W; ++b)
+      if (red >> b & 1u) acc[b] ^= acc[i];
+  }
+}
+
+template <int W, int V>
+__device__ __forceinline__ void load_block(typename Vec<V>::T (&d)[W], const uint8_t *base,
+                                           uint32_t S, uint32_t col) {
+  const __amdgpu_buffer_rsrc_t r = block_rsrc(base, W * S);
+#pragma unroll
+  for (int t = 0; t < W; ++t) d[t] = bload<V>(r, col, t * S);
+}
+
+// One lane column of one pass.  Src supplies wave-uniform values:
+//   k(), S(), in(j), out(r), lift(j, r).
+template <int W, int N, uint32_t P, int MO, int V, class Src>
+__device__ __forceinline__ void code_column(const Src &src, uint32_t col, bool live) {
+  typedef typename Vec<V>::T T;
+  const int k = src.k();
+  const uint32_t S = src.S();
+  T acc[MO][N];
+#pragma unroll
+  for (int r = 0; r < MO; ++r)
+#pragma unroll
+    for (int i = 0; i < N; ++i) acc[r][i] = (T)0;
+
+  // Two register sets: block j+1 is in flight while block j is accumulated.
+  // Past the last block the prefetch repeats block k-1, which the cache
+  // still holds.
+  T dA[W], dB[W];
+  load_block<W, V>(dA, src.in(0), S, col);
+  for (int j = 0; j < k; j += 2) {
+    load_block<W, V>(dB, src.in(j + 1 < k ? j + 1 : k - 1), S, col);
+#pragma unroll
+    for (int r = 0; r < MO; ++r) rot_acc<W, N, 0, T>(acc[r], dA, src.lift(j, r));
+    if (j + 1 >= k) break;
+    load_block<W, V>(dA, src.in(j + 2 < k ? j + 2 : k - 1), S, col);
+#pragma unroll
+    for (int r = 0; r < MO; ++r) rot_acc<W, N, 0, T>(acc[r], dB, src.lift(j + 1, r));
+  }
+
+  if (!live) return;
+#pragma unroll
+  for (int r = 0; r < MO; ++r) {
+    reduce_mod_p<W, N, P, T>(acc[r]);
+    const __amdgpu_buffer_rsrc_t o = block_rsrc(src.out(r), W * S);
+#pragma unroll
+    for (int t = 0; t < W; ++t) bstore<V>(acc[r][t], o, col, t * S);
+  }
+}
+
+// Source of pass arguments held in the kernel-argument segment.
+struct KernargSrc {
+  const PassArgs &a;
+  __device__ int k() const { return (int)a.k; }
+  __device__ uint32_t S() const { return a.S; }
+  __device__ const uint8_t *in(int j) const { return a.in[j]; }
+  __device__ uint8_t *out(int r) const { return a.out[r]; }
+  __device__ uint32_t lift(int j, int r) const { return a.lift[j][r]; }
+};
+
+}  // namespace dev
+}  // namespace pyrit

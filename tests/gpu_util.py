@@ -1,0 +1,53 @@
+"""Helpers shared by the GPU parity tests: device buffers filled with the
+seeded generator, and oracle expectations on sampled columns."""
+import numpy as np
+
+import oracle
+import paper_1709_00178_amd as P
+from paper_1709_00178_amd import workloads as W
+
+
+def torch_mod():
+    import torch
+    return torch
+
+
+def dev_empty(nbytes):
+    torch = torch_mod()
+    return torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+
+
+def dev_block(st, block_id):
+    """A device block holding the generator's bytes for block `block_id`."""
+    t = dev_empty(st.block_len)
+    P.fill_random(t, st.key(block_id), nrandom=st.B)
+    return t
+
+
+def to_host(t):
+    return t.cpu().numpy()
+
+
+def gather_cols(buf, S, w, cols):
+    """Mini block made of the given columns of every slice (w x len(cols))."""
+    return np.ascontiguousarray(np.stack([buf[t * S + cols] for t in range(w)]).reshape(-1))
+
+
+def gen_cols(st, block_id, cols):
+    """Generator bytes of a block at the given columns of every slice."""
+    offs = (np.arange(st.w)[:, None] * st.S + cols[None, :]).reshape(-1)
+    return W.block_bytes_at(st.key(block_id), offs, st.B)
+
+
+def sample_cols(S, n, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    extra = np.array([0, 1, 15, 16, 63, S - 64, S - 17, S - 16, S - 1])
+    cols = np.unique(np.concatenate([rng.integers(0, S, n), extra]))
+    return cols[(cols >= 0) & (cols < S)]
+
+
+def oracle_cols(st, G, in_ids, cols, nthreads=4):
+    """Oracle outputs (rows of G applied to the input blocks) at `cols`."""
+    f = oracle.Field(st.w, st.p)
+    ins = [gen_cols(st, j, cols) for j in in_ids]
+    return f.encode(np.ascontiguousarray(G, dtype=np.uint16), ins, len(cols), nthreads=nthreads)

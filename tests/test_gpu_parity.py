@@ -1,0 +1,287 @@
+"""GPU outputs against the CPU oracle, bit-exact, through the C ABI."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1709_00178_amd as P
+from paper_1709_00178_amd import workloads as W
+from tests.gpu_util import (dev_block, dev_empty, gather_cols, gen_cols, oracle_cols, sample_cols,
+                            to_host, torch_mod)
+
+pytestmark = pytest.mark.gpu
+
+RINGS = [(4, 5, 0x1F), (8, 17, 0x139), (8, 17, 0x1D7), (10, 11, 0x7FF), (6, 9, 0x49)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    torch = torch_mod()
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    oracle.build()
+    yield
+    torch.cuda.synchronize()
+
+
+def sync():
+    torch_mod().cuda.synchronize()
+
+
+def test_fill_random_matches_generator():
+    for nbytes, nrandom, key in [(1 << 20, 1 << 20, 1), (4096, 1000, 12345), (64, 3, 2**64 - 5)]:
+        t = dev_empty(nbytes)
+        P.fill_random(t, key, nrandom=nrandom)
+        got = to_host(t)
+        assert np.array_equal(got, W.block_bytes(key, nbytes, nrandom))
+
+
+def test_copy_kernel():
+    src = dev_empty(1 << 20)
+    P.fill_random(src, 7)
+    dst = dev_empty(1 << 20)
+    P.copy(dst, src)
+    assert np.array_equal(to_host(dst), to_host(src))
+
+
+def _full_check(st, G, vec_bytes=0, seed_ids=None):
+    """Encode a whole stripe on the GPU and compare every byte with the oracle."""
+    k, m = G.shape[1], G.shape[0]
+    plan = P.Plan(st.w, st.n, st.p, k, m, G=G)
+    data = [dev_block(st, j) for j in range(k)]
+    par = [dev_empty(st.block_len) for _ in range(m)]
+    for t in par:
+        t.fill_(0xA5)
+    plan.encode(data, par, st.S, vec_bytes=vec_bytes)
+    sync()
+    host = [W.block_bytes(st.key(j), st.block_len, st.B) for j in range(k)]
+    want = oracle.Field(st.w, st.p).encode(G, host, st.S, nthreads=4)
+    for i in range(m):
+        got = to_host(par[i])
+        assert np.array_equal(got, want[i]), f"parity {i} differs at {np.flatnonzero(got != want[i])[:8]}"
+
+
+@pytest.mark.parametrize("vec", [0, 4, 8, 16])
+def test_c0_encode_bit_exact(vec):
+    st = W.c0()
+    _full_check(st, P.cauchy(st.w, st.p, st.k, st.m), vec_bytes=vec)
+
+
+def test_c0_decode_every_two_erasure_pattern():
+    st = W.c0()
+    torch = torch_mod()
+    f = oracle.Field(st.w, st.p)
+    plan = P.Plan(st.w, st.n, st.p, st.k, st.m)
+    data = W.host_blocks(st)
+    code = data + f.encode(plan.G, data, st.S, nthreads=4)
+    dev = [torch.from_numpy(b).cuda() for b in code]
+    pats = W.c0_erasure_patterns() + [(e,) for e in range(6)]
+    for er in pats:
+        blocks = [b.clone() for b in dev]
+        for e in er:
+            blocks[e].fill_(0x5A)
+        plan.decode(list(er), blocks, st.S)
+        sync()
+        for i in range(6):
+            assert np.array_equal(to_host(blocks[i]), code[i]), (er, i)
+
+
+# S spans several 256-lane workgroups and ends in a ragged tail for every
+# lane width (4, 8 and 16 bytes per lane).
+RAGGED_S = 64 * (4 * 256 + 3)
+
+
+@pytest.mark.parametrize("w,n,p", RINGS)
+@pytest.mark.parametrize("vec", [4, 8, 16])
+def test_random_matrix_ragged_sizes(w, n, p, vec):
+    k, m = 5, 4
+    rng = np.random.Generator(np.random.PCG64(w * 100 + vec))
+    G = rng.integers(0, 1 << w, size=(m, k)).astype(np.uint16)
+    st = W.Stripe(w, n, p, k=k, m=m, B=RAGGED_S * w - 40, stripe=w + vec, seed=99)
+    assert st.S == RAGGED_S
+    _full_check(st, G, vec_bytes=vec)
+
+
+@pytest.mark.parametrize("w,n,p,k,m", [(8, 17, 0x139, 8, 6), (10, 11, 0x7FF, 12, 9),
+                                       (4, 5, 0x1F, 3, 1), (6, 9, 0x49, 40, 20)])
+def test_many_outputs_and_shapes(w, n, p, k, m):
+    st = W.Stripe(w, n, p, k=k, m=m, B=64 * 300 * w, stripe=k, seed=5)
+    _full_check(st, P.cauchy(w, p, k, m))
+
+
+@pytest.mark.parametrize("w,n,p", [(8, 17, 0x139), (10, 11, 0x7FF), (4, 5, 0x1F)])
+def test_minimum_slice_and_single_input(w, n, p):
+    st = W.Stripe(w, n, p, k=1, m=3, B=64 * w, seed=6)
+    assert st.S == 64
+    _full_check(st, np.array([[1], [2], [(1 << w) - 1]], dtype=np.uint16))
+
+
+def test_xor_parity_closed_form():
+    """An all-ones row: parity = XOR of the data blocks (RAID-5)."""
+    st = W.Stripe(8, 17, 0x139, k=7, m=1, B=8 * 4096, seed=8)
+    plan = P.Plan(st.w, st.n, st.p, 7, 1, G=np.ones((1, 7), dtype=np.uint16))
+    data = [dev_block(st, j) for j in range(7)]
+    par = [dev_empty(st.block_len)]
+    plan.encode(data, par, st.S)
+    sync()
+    want = np.bitwise_xor.reduce(np.stack([W.block_bytes(st.key(j), st.block_len) for j in range(7)]))
+    assert np.array_equal(to_host(par[0]), want)
+
+
+@pytest.mark.parametrize("s", [1, 5, 7])
+def test_multiply_by_x_power_closed_form(s):
+    """G = [x^s]: shift slices up by s, folding each overflow through p."""
+    w, n, p, S = 8, 17, 0x139, 4096
+    st = W.Stripe(w, n, p, k=1, m=1, B=w * S, seed=9 + s)
+    plan = P.Plan(w, n, p, 1, 1, G=np.array([[1 << s]], dtype=np.uint16))
+    d = dev_block(st, 0)
+    out = dev_empty(st.block_len)
+    plan.encode([d], [out], S)
+    sync()
+    host = W.block_bytes(st.key(0), st.block_len)
+    sl = [host[t * S:(t + 1) * S].copy() for t in range(w)]
+    for _ in range(s):
+        top = sl[w - 1]
+        sl = [np.zeros(S, dtype=np.uint8)] + sl[:w - 1]
+        for t in range(w):
+            if (p >> t) & 1:
+                sl[t] = sl[t] ^ top
+    assert np.array_equal(to_host(out), np.concatenate(sl))
+
+
+def test_c1_full_size_encode_sampled():
+    """GF(2^8) k=10 m=4, 64 MiB blocks: every launch shape the benchmark uses,
+    checked on sampled columns of every slice of every parity block."""
+    st = W.c1()
+    plan = P.Plan(st.w, st.n, st.p, st.k, st.m)
+    data = [dev_block(st, j) for j in range(st.k)]
+    cols = sample_cols(st.S, 2048, 1)
+    want = oracle_cols(st, plan.G, range(st.k), cols)
+    for vec in [0, 8]:
+        par = [dev_empty(st.block_len) for _ in range(st.m)]
+        plan.encode(data, par, st.S, vec_bytes=vec)
+        sync()
+        for i in range(st.m):
+            got = gather_cols(to_host(par[i]), st.S, st.w, cols)
+            assert np.array_equal(got, want[i]), (vec, i)
+
+
+def test_c1_decode_roundtrip_full_size():
+    """Encode, erase the workload's patterns, decode: recovered data blocks
+    equal the generator's bytes everywhere; recovered parity equals the oracle
+    on sampled columns."""
+    st = W.c1()
+    plan = P.Plan(st.w, st.n, st.p, st.k, st.m)
+    code = [dev_block(st, j) for j in range(st.k)] + [dev_empty(st.block_len) for _ in range(st.m)]
+    plan.encode(code[:st.k], code[st.k:], st.S)
+    cols = sample_cols(st.S, 1024, 2)
+    want_par = oracle_cols(st, plan.G, range(st.k), cols)
+    for er in W.c1_erasure_patterns():
+        blocks = [b.clone() for b in code]
+        for e in er:
+            blocks[e].fill_(0xC3)
+        plan.decode(list(er), blocks, st.S)
+        sync()
+        for e in er:
+            got = to_host(blocks[e])
+            if e < st.k:
+                assert np.array_equal(got, W.block_bytes(st.key(e), st.block_len, st.B)), (er, e)
+            else:
+                assert np.array_equal(gather_cols(got, st.S, st.w, cols), want_par[e - st.k]), (er, e)
+
+
+def test_c2_all_stripes_sampled():
+    """GF(2^10) k=16 m=4, 256 stripes of 4 MiB blocks, plain kernel per stripe."""
+    stripes = W.c2()
+    st0 = stripes[0]
+    plan = P.Plan(st0.w, st0.n, st0.p, st0.k, st0.m)
+    torch = torch_mod()
+    cols = sample_cols(st0.S, 24, 3)
+    data = torch.empty((len(stripes), st0.k, st0.block_len), dtype=torch.uint8, device="cuda")
+    par = torch.empty((len(stripes), st0.m, st0.block_len), dtype=torch.uint8, device="cuda")
+    for s, st in enumerate(stripes):
+        for j in range(st.k):
+            P.fill_random(data[s, j], st.key(j), nrandom=st.B)
+        plan.encode([data[s, j] for j in range(st.k)], [par[s, i] for i in range(st.m)], st.S)
+    sync()
+    idx = torch.as_tensor((np.arange(st0.w)[:, None] * st0.S + cols[None, :]).reshape(-1),
+                          device="cuda")
+    got_all = par[:, :, idx].cpu().numpy()
+    for s, st in enumerate(stripes):
+        want = oracle_cols(st, plan.G, range(st.k), cols, nthreads=2)
+        for i in range(st.m):
+            assert np.array_equal(got_all[s, i], want[i]), (s, i)
+
+
+def test_c3_stripes_plain_sampled():
+    """The uneven batch distribution through the plain path, first 192 stripes."""
+    torch = torch_mod()
+    plans = {}
+    for st in W.c3()[:192]:
+        key = (st.w, st.k, st.m)
+        if key not in plans:
+            plans[key] = P.Plan(st.w, st.n, st.p, st.k, st.m)
+        plan = plans[key]
+        ins = W.survivors(st)
+        blocks = [None] * (st.k + st.m)
+        for b in ins:
+            blocks[b] = dev_block(st, b)
+        outs = list(st.erased) if st.erased else list(range(st.k, st.k + st.m))
+        for b in outs:
+            blocks[b] = dev_empty(st.block_len)
+        if st.erased:
+            # survivors not read by the decoder may be absent; give them a buffer anyway
+            for b in range(st.k + st.m):
+                if blocks[b] is None:
+                    blocks[b] = dev_empty(64)
+            plan.decode(list(st.erased), blocks, st.S)
+            _, D = plan.decode_matrix(list(st.erased))
+            G = D
+        else:
+            plan.encode(blocks[:st.k], blocks[st.k:], st.S)
+            G = plan.G
+        sync()
+        cols = sample_cols(st.S, 16, st.stripe)
+        want = oracle_cols(st, G, ins, cols, nthreads=1)
+        for r, b in enumerate(outs):
+            got = gather_cols(to_host(blocks[b]), st.S, st.w, cols)
+            assert np.array_equal(got, want[r]), (st, b)
+    del torch
+
+
+def test_parity_only_and_empty_erasures():
+    st = W.Stripe(10, 11, 0x7FF, k=6, m=4, B=10 * 64 * 64, seed=11)
+    plan = P.Plan(st.w, st.n, st.p, st.k, st.m)
+    torch = torch_mod()
+    f = oracle.Field(st.w, st.p)
+    data = W.host_blocks(st)
+    code = data + f.encode(plan.G, data, st.S)
+    dev = [torch.from_numpy(b).cuda() for b in code]
+    for er in [(6, 9), (7,), (6, 7, 8, 9), ()]:
+        blocks = [b.clone() for b in dev]
+        for e in er:
+            blocks[e].zero_()
+        plan.decode(list(er), blocks, st.S)
+        sync()
+        for i in range(st.k + st.m):
+            assert np.array_equal(to_host(blocks[i]), code[i]), (er, i)
+
+
+def test_error_paths():
+    st = W.Stripe(8, 17, 0x139, k=2, m=2, B=8 * 256, seed=12)
+    plan = P.Plan(st.w, st.n, st.p, 2, 2)
+    a = dev_empty(st.block_len + 64)
+    bufs = [dev_empty(st.block_len) for _ in range(3)]
+    with pytest.raises(P.PyritError) as e:
+        plan.encode([a.data_ptr() + 1, bufs[0]], bufs[1:], st.S)
+    assert e.value.code == -8
+    with pytest.raises(P.PyritError) as e:
+        plan.encode([a, bufs[0]], bufs[1:], 100)
+    assert e.value.code == -8
+    with pytest.raises(P.PyritError) as e:
+        plan.decode([0, 1, 2], [a] + bufs, st.S)
+    assert e.value.code == -6
+    with pytest.raises(P.PyritError) as e:
+        plan.encode([a, bufs[0]], bufs[1:], st.S, vec_bytes=12)
+    assert e.value.code == -1
+    sync()
