@@ -1,10 +1,12 @@
 """Benchmark: encode throughput of GF(2^8) k=10 m=4 with 64 MiB blocks on one
-MI355X, plus roofline, decode and CPU-oracle baselines.
+MI355X through the batched persistent kernel (hipGraph replay), beside the
+plain per-stripe kernel, decode, the 256-stripe and 4096-stripe batches, the
+HBM roofline and the CPU oracle.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--only c1,c2,c3]
 
 Prints ONE JSON line.  A step is one encode of the whole stripe (10 data
-blocks of 64 MiB, 4 parity blocks), inputs already resident in HBM.
+blocks of 64 MiB, 4 parity blocks of 64 MiB), inputs already resident in HBM.
 """
 from __future__ import annotations
 
@@ -20,7 +22,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, 8 TB/s
 KERNEL_SOURCES = ["paper_1709_00178_amd/csrc/ring_kernels.hpp",
-                  "paper_1709_00178_amd/csrc/plain_impl.hpp"]
+                  "paper_1709_00178_amd/csrc/plain_impl.hpp",
+                  "paper_1709_00178_amd/csrc/batch.hip"]
 
 
 def kernel_hash() -> str:
@@ -32,8 +35,9 @@ def kernel_hash() -> str:
 
 
 def traffic_record(name: str):
-    """HBM traffic measured by rocprofv3 counters for this kernel source, if
-    the record matches the current kernel sources."""
+    """HBM bytes per launch measured with rocprofv3 counters (FETCH_SIZE and
+    WRITE_SIZE, calibrated on a copy kernel) for the current kernel sources;
+    None when no record matches them."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -44,24 +48,71 @@ def traffic_record(name: str):
     return rec.get("bytes_per_launch")
 
 
-def time_launches(fn, reps, stream):
-    """Average device duration of fn() launches, from HIP events recorded on
-    the stream the kernels run on."""
+def batch_time_ms(fn, reps, stream):
+    """Average device time per call of fn(), from HIP events recorded on the
+    stream the kernels run on, around `reps` back-to-back calls."""
+    import torch
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    b.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def per_call_ms(fn, reps, stream):
+    """Per-call device times (events around each call): for p50 / p99."""
     import torch
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(reps)]
-    for a, b in evs:
-        a.record(stream)
+    for x, y in evs:
+        x.record(stream)
         fn()
-        b.record(stream)
+        y.record(stream)
     torch.cuda.synchronize()
-    ms = [a.elapsed_time(b) for a, b in evs]
-    ms.sort()
-    return sum(ms) / len(ms), ms[len(ms) // 2], ms[min(len(ms) - 1, int(0.99 * len(ms)))]
+    ms = sorted(x.elapsed_time(y) for x, y in evs)
+    return ms[len(ms) // 2], ms[min(len(ms) - 1, int(round(0.99 * (len(ms) - 1))))]
+
+
+class Arena:
+    def __init__(self, nbytes):
+        import torch
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.off = 0
+
+    def take(self, nbytes):
+        off = self.off
+        self.off = off + (nbytes + 255) // 256 * 256
+        assert self.off <= self.buf.numel()
+        return self.buf[off:off + nbytes]
+
+
+def stripe_buffers(st, arena):
+    import paper_1709_00178_amd as P
+    from paper_1709_00178_amd import workloads as W
+    ins = list(W.survivors(st))
+    outs = list(st.erased) if st.erased else list(range(st.k, st.k + st.m))
+    blocks = [None] * (st.k + st.m)
+    for b in ins:
+        blocks[b] = arena.take(st.block_len)
+        P.fill_random(blocks[b], st.key(b), nrandom=st.B)
+    for b in outs:
+        blocks[b] = arena.take(st.block_len)
+    return blocks
+
+
+def arena_bytes(stripes):
+    tot = 0
+    for st in stripes:
+        n_out = len(st.erased) if st.erased else st.m
+        tot += (st.k + n_out) * ((st.block_len + 255) // 256 * 256)
+    return tot + 4096
 
 
 def cpu_baseline(target_s: float = 10.0):
-    """The CPU oracle encoding a column sample of the same code, all host cores."""
+    """The CPU oracle encoding a column sample of the same code on all host
+    cores (the oracle as written: plain log/antilog tables, OpenMP)."""
     import numpy as np
 
     import oracle
@@ -69,7 +120,7 @@ def cpu_baseline(target_s: float = 10.0):
     st = W.c1()
     f = oracle.Field(st.w, st.p)
     C = f.cauchy(st.k, st.m)
-    Sp = 4 << 20  # 4 MiB of columns from every slice
+    Sp = 4 << 20
     data = [W.block_bytes(st.key(j), st.w * Sp) for j in range(st.k)]
     nt = oracle.max_threads()
     par = [np.zeros(st.w * Sp, dtype=np.uint8) for _ in range(st.m)]
@@ -82,8 +133,159 @@ def cpu_baseline(target_s: float = 10.0):
             break
     gbps = st.k * st.w * Sp * reps / el / 1e9
     return {"value": round(gbps, 4), "unit": "GB/s", "cores": nt, "kind": "oracle",
-            "sample": f"GF(2^8) k=10 m=4 Cauchy code on a {Sp >> 20} MiB column sample of every "
-                      f"slice ({st.k * st.w * Sp / 1e6:.0f} MB of data), {reps} passes, {el:.1f} s"}
+            "sample": f"GF(2^8) k=10 m=4 Cauchy encode of a {Sp >> 20} MiB column sample of every "
+                      f"slice ({st.k * st.w * Sp / 1e6:.0f} MB of data) x {reps} passes, {el:.1f} s"}
+
+
+def bench_c1(args, stream, out):
+    import torch
+
+    import paper_1709_00178_amd as P
+    from paper_1709_00178_amd import workloads as W
+    st = W.c1()
+    plan = P.Plan(st.w, st.n, st.p, st.k, st.m)
+    arena = Arena(arena_bytes([st]))
+    blocks = stripe_buffers(st, arena)
+    data, par = blocks[:st.k], blocks[st.k:]
+    batch = P.Batch([(plan, [], blocks, st.S)])
+    torch.cuda.synchronize()
+
+    def enc_batched():
+        batch.launch(stream)
+
+    def enc_plain():
+        plan.encode(data, par, st.S, stream=stream)
+
+    for _ in range(args.warmup):
+        enc_batched()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        enc_batched()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+
+    moved = st.moved_bytes()
+    reps = max(20, args.steps)
+    b_ms = batch_time_ms(enc_batched, reps, stream)
+    b_p50, b_p99 = per_call_ms(enc_batched, 20, stream)
+    for _ in range(3):
+        enc_plain()
+    p_ms = batch_time_ms(enc_plain, reps, stream)
+    p_p50, p_p99 = per_call_ms(enc_plain, 20, stream)
+
+    # decode of the workload's random 4-erasure pattern: the stripe is a valid
+    # codeword, so the erased blocks are rewritten with the bytes they hold
+    er = list(W.c1_erasure_patterns()[0])
+    dbatch = P.Batch([(plan, er, blocks, st.S)])
+    for _ in range(3):
+        plan.decode(er, blocks, st.S, stream=stream)
+        dbatch.launch(stream)
+    d_plain = batch_time_ms(lambda: plan.decode(er, blocks, st.S, stream=stream), 20, stream)
+    d_batch = batch_time_ms(lambda: dbatch.launch(stream), 20, stream)
+    d_moved = (st.k + len(er)) * st.block_len
+
+    info = batch.info()
+    achieved = moved / (b_ms * 1e-3) / 1e9
+    out.update({
+        "value": round(st.k * st.B * args.steps / el / 1e9, 2),
+        "ms_per_step": round(el * 1e3 / args.steps, 4),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": traffic_record("batch_c1"),
+                     "kernel": "pyrit::batch_kernel<256>",
+                     "algorithmic_bytes_per_launch": moved,
+                     "avg_launch_ms": round(b_ms, 4)},
+        "c1": {
+            "batched": {"GBps_data": round(st.k * st.B / (b_ms * 1e-3) / 1e9, 1),
+                        "GBps_moved": round(achieved, 1), "avg_ms": round(b_ms, 4),
+                        "p50_ms": round(b_p50, 4), "p99_ms": round(b_p99, 4),
+                        "grid": info["grid"], "work_items": info["work_items"]},
+            "plain": {"GBps_data": round(st.k * st.B / (p_ms * 1e-3) / 1e9, 1),
+                      "GBps_moved": round(moved / (p_ms * 1e-3) / 1e9, 1),
+                      "avg_ms": round(p_ms, 4), "p50_ms": round(p_p50, 4),
+                      "p99_ms": round(p_p99, 4)},
+            "decode_4_erasures": {"erased": er,
+                                  "plain_GBps_moved": round(d_moved / (d_plain * 1e-3) / 1e9, 1),
+                                  "batched_GBps_moved": round(d_moved / (d_batch * 1e-3) / 1e9, 1),
+                                  "plain_ms": round(d_plain, 4), "batched_ms": round(d_batch, 4)},
+        },
+    })
+    # device copy of the same byte volume: a bandwidth reference
+    half = (moved // 2) // 16 * 16
+    src = torch.empty(half, dtype=torch.uint8, device="cuda")
+    dst = torch.empty(half, dtype=torch.uint8, device="cuda")
+    P.copy(dst, src, stream=stream)
+    cp_ms = batch_time_ms(lambda: P.copy(dst, src, stream=stream), 20, stream)
+    out["copy_ceiling_GBps"] = round(2 * half / (cp_ms * 1e-3) / 1e9, 1)
+    del batch, dbatch, arena
+    torch.cuda.empty_cache()
+
+
+def bench_c2(args, stream, out):
+    import torch
+
+    import paper_1709_00178_amd as P
+    from paper_1709_00178_amd import workloads as W
+    stripes = W.c2()
+    st0 = stripes[0]
+    plan = P.Plan(st0.w, st0.n, st0.p, st0.k, st0.m)
+    arena = Arena(arena_bytes(stripes))
+    bl = [stripe_buffers(st, arena) for st in stripes]
+    batch = P.Batch([(plan, [], b, st.S) for st, b in zip(stripes, bl)])
+    torch.cuda.synchronize()
+
+    def plain_all():
+        for st, b in zip(stripes, bl):
+            plan.encode(b[:st.k], b[st.k:], st.S, stream=stream)
+
+    plain_all()
+    batch.launch(stream)
+    p_ms = batch_time_ms(plain_all, 5, stream)
+    b_ms = batch_time_ms(lambda: batch.launch(stream), 10, stream)
+    moved = sum(s.moved_bytes() for s in stripes)
+    user = sum(s.k * s.B for s in stripes)
+    out["c2"] = {"stripes": len(stripes),
+                 "plain_256_launches": {"ms": round(p_ms, 3),
+                                        "GBps_data": round(user / (p_ms * 1e-3) / 1e9, 1),
+                                        "GBps_moved": round(moved / (p_ms * 1e-3) / 1e9, 1)},
+                 "batched_1_launch": {"ms": round(b_ms, 3),
+                                      "GBps_data": round(user / (b_ms * 1e-3) / 1e9, 1),
+                                      "GBps_moved": round(moved / (b_ms * 1e-3) / 1e9, 1),
+                                      "frac_of_peak": round(moved / (b_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                                      "work_items": batch.info()["work_items"]}}
+    del batch, arena, bl
+    torch.cuda.empty_cache()
+
+
+def bench_c3(args, stream, out):
+    import torch
+
+    import paper_1709_00178_amd as P
+    from paper_1709_00178_amd import workloads as W
+    stripes = W.c3()
+    plans = {}
+    for st in stripes:
+        key = (st.w, st.n, st.p, st.k, st.m)
+        if key not in plans:
+            plans[key] = P.Plan(*key)
+    arena = Arena(arena_bytes(stripes))
+    bl = [stripe_buffers(st, arena) for st in stripes]
+    t0 = time.perf_counter()
+    batch = P.Batch([(plans[(st.w, st.n, st.p, st.k, st.m)], list(st.erased), b, st.S)
+                     for st, b in zip(stripes, bl)])
+    build_s = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    batch.launch(stream)
+    b_ms = batch_time_ms(lambda: batch.launch(stream), 10, stream)
+    moved = batch.info()["moved_bytes"]
+    out["c3"] = {"stripes": len(stripes), "decodes": sum(1 for s in stripes if s.erased),
+                 "moved_GB": round(moved / 1e9, 3), "ms": round(b_ms, 3),
+                 "GBps_moved": round(moved / (b_ms * 1e-3) / 1e9, 1),
+                 "frac_of_peak": round(moved / (b_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                 "batch_build_s": round(build_s, 3), "work_items": batch.info()["work_items"]}
+    del batch, arena, bl
+    torch.cuda.empty_cache()
 
 
 def main():
@@ -92,97 +294,37 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--vec", type=int, default=0, help="lane width for the plain kernel")
+    ap.add_argument("--only", default="c1,c2,c3", help="comma list of c1,c2,c3")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the coding path shards stripes or column ranges across GPUs with no exchange; "
-              "this build runs and reports a single GPU)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported. Stripes (or "
+              "column ranges of one stripe) shard across GPUs with no exchange, but this "
+              "build runs and reports a single GPU only.", file=sys.stderr)
         sys.exit(2)
 
     import torch
-
-    import paper_1709_00178_amd as P
-    from paper_1709_00178_amd import workloads as W
-
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    from paper_1709_00178_amd import workloads as W
     st = W.c1()
-    plan = P.Plan(st.w, st.n, st.p, st.k, st.m)
-    data = [torch.empty(st.block_len, dtype=torch.uint8, device="cuda") for _ in range(st.k)]
-    for j, t in enumerate(data):
-        P.fill_random(t, st.key(j), nrandom=st.B)
-    par = [torch.empty(st.block_len, dtype=torch.uint8, device="cuda") for _ in range(st.m)]
-    torch.cuda.synchronize()
-
-    def encode():
-        plan.encode(data, par, st.S, vec_bytes=args.vec)
-
-    for _ in range(args.warmup):
-        encode()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        encode()
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    user_bytes = st.k * st.B
-    moved = st.moved_bytes()
-    value = user_bytes * args.steps / el / 1e9
-
-    avg_ms, p50_ms, p99_ms = time_launches(encode, max(20, args.steps), stream)
-    achieved = moved / (avg_ms * 1e-3) / 1e9
-
-    # decode of the workload's random 4-erasure pattern through the same kernel
-    er = list(W.c1_erasure_patterns()[0])
-    blocks = data + par
-
-    # The stripe is a valid codeword, so decoding rewrites the erased blocks
-    # with the bytes they already hold.
-    def decode():
-        plan.decode(er, blocks, st.S)
-
-    for _ in range(3):
-        decode()
-    dec_ms, _, dec_p99 = time_launches(decode, 20, stream)
-    dec_moved = (st.k + len(er)) * st.block_len
-
-    # device copy of the same byte volume: practical bandwidth reference
-    half = (moved // 2) // 16 * 16
-    src = torch.empty(half, dtype=torch.uint8, device="cuda")
-    dst = torch.empty(half, dtype=torch.uint8, device="cuda")
-    P.copy(dst, src)
-    cp_ms, _, _ = time_launches(lambda: P.copy(dst, src), 20, stream)
-    copy_gbps = 2 * half / (cp_ms * 1e-3) / 1e9
-
     out = {
-        "metric": "encode GB/s (GF(2^8) k=10 m=4, 64 MiB blocks)",
-        "value": round(value, 2),
-        "unit": "GB/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(el * 1e3 / args.steps, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u8",
-        "data": "synthetic (seeded SplitMix64 bytes generated in HBM)",
-        "config": {"workload": "GF(2^8) in R_{2,17}, p=x^8+x^5+x^4+x^3+1, Cauchy k=10 m=4, "
-                               "one stripe of 64 MiB blocks (8 slices of 8 MiB), plain kernel",
+        "metric": "encode GB/s of data (GF(2^8) k=10 m=4, 64 MiB blocks), batched persistent kernel",
+        "value": None, "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u8", "data": "synthetic (seeded SplitMix64 bytes generated in HBM)",
+        "config": {"workload": "GF(2^8) in R_{2,17}, p = x^8+x^5+x^4+x^3+1, Cauchy k=10 m=4, one "
+                               "stripe of 64 MiB blocks (8 slices of 8 MiB), batched persistent "
+                               "kernel replayed as a hipGraph",
                    "k": st.k, "m": st.m, "w": st.w, "n": st.n, "block_bytes": st.B,
                    "slice_bytes": st.S, "parallelism": "1 GPU"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": traffic_record("plain_c1"),
-                     "kernel": "plain_pass_kernel<ring (8,17,0x139), 4 outputs>",
-                     "algorithmic_bytes_per_launch": moved,
-                     "avg_launch_ms": round(avg_ms, 4), "p50_launch_ms": round(p50_ms, 4),
-                     "p99_launch_ms": round(p99_ms, 4)},
-        "decode": {"erased": er, "GBps_moved": round(dec_moved / (dec_ms * 1e-3) / 1e9, 1),
-                   "avg_ms": round(dec_ms, 4), "p99_ms": round(dec_p99, 4)},
-        "copy_ceiling_GBps": round(copy_gbps, 1),
     }
+    only = set(args.only.split(","))
+    if "c1" in only:
+        bench_c1(args, stream, out)
+    if "c2" in only:
+        bench_c2(args, stream, out)
+    if "c3" in only:
+        bench_c3(args, stream, out)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

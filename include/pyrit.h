@@ -165,6 +165,60 @@ int pyrit_fill_random(uint8_t *dst, size_t nbytes, size_t nrandom, uint64_t key,
  * per lane); nbytes a multiple of 16.  A bandwidth reference. */
 int pyrit_copy(uint8_t *dst, const uint8_t *src, size_t nbytes, void *stream);
 
+/* ------------------------------------------------------------------ batches
+ * Many stripes (any mix of supported rings, k, m, slice sizes, encodes and
+ * decodes) coded by ONE persistent kernel launch.  Each stripe is split into
+ * passes of at most four outputs and each pass into column tiles; the tiles
+ * form a device work queue that resident waves drain.  The launch is a
+ * hipGraph with a single kernel node, replayed by pyrit_batch_launch.  The
+ * output bytes of every stripe equal those of pyrit_encode / pyrit_decode on
+ * the same inputs.
+ */
+typedef struct {
+  const pyrit_plan *plan;   /* code of this stripe (must outlive the batch) */
+  int n_erased;             /* 0: encode all m parity blocks; else: decode */
+  const int *erased;        /* n_erased distinct block ids (host, copied) */
+  uint8_t *const *blocks;   /* k + m device pointers (host array, copied):
+                               data then parity; outputs are the parity
+                               blocks (encode) or the erased blocks (decode);
+                               the first k non-erased blocks are inputs */
+  size_t slice_bytes;       /* S of this stripe */
+} pyrit_batch_item;
+
+typedef struct {
+  int tile_bytes;   /* column bytes per work item; 0 = library choice */
+  int grid;         /* resident workgroups; 0 = 256 CUs x occupancy */
+  int wg_threads;   /* 64, 128 or 256 threads per workgroup; 0 = 256 */
+  int static_queue; /* 0 = atomic work queue (default); 1 = static stride */
+} pyrit_tune;
+
+typedef struct pyrit_batch pyrit_batch;
+
+/* Validate every item, build the work queue (host), upload descriptors and
+ * pointer tables to device memory (one allocation owned by the batch) and
+ * instantiate the hipGraph.  Nothing runs on the GPU yet.  tune may be NULL.
+ * Items are validated like pyrit_encode / pyrit_decode; the first failing
+ * item's code is returned and no batch is created. */
+int pyrit_batch_create(const pyrit_batch_item *items, int n_items, const pyrit_tune *tune,
+                       pyrit_batch **out);
+
+/* Enqueue one execution of the batch on stream (graph replay).  A batch
+ * must not run concurrently with itself (its queue counters are shared);
+ * distinct batches may run concurrently on distinct streams. */
+int pyrit_batch_launch(pyrit_batch *batch, void *stream);
+
+/* Same work as pyrit_batch_launch, as a direct kernel launch (no graph). */
+int pyrit_batch_launch_direct(pyrit_batch *batch, void *stream);
+
+/* Facts about a batch (any pointer may be NULL): passes, work items, bytes
+ * the batch reads and writes ((k + outputs) * w * S summed), and the
+ * workgroups and threads per workgroup it launches. */
+int pyrit_batch_info(const pyrit_batch *batch, int *n_passes, int *n_work_items,
+                     uint64_t *moved_bytes, int *grid, int *wg_threads);
+
+/* Release the batch.  The caller must ensure no stream still runs it. */
+void pyrit_batch_destroy(pyrit_batch *batch);
+
 #ifdef __cplusplus
 }
 #endif

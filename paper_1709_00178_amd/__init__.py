@@ -14,7 +14,7 @@ import numpy as np
 
 from ._lib import lib
 
-__all__ = ["PyritError", "Plan", "ring_check", "ring_supported", "lift", "ring_reduce",
+__all__ = ["PyritError", "Plan", "Batch", "ring_check", "ring_supported", "lift", "ring_reduce",
            "ring_mul", "gf_mul", "cauchy", "fill_random", "copy", "version"]
 
 PYRIT_OK = 0
@@ -166,6 +166,62 @@ class Plan:
         er = (ctypes.c_int * max(1, len(erased)))(*erased)
         _check(lib().pyrit_decode(self._h, er, len(erased), _ptr_array(blocks), S,
                                   _stream_handle(stream)))
+
+
+class Batch:
+    """Many stripes coded by one persistent-kernel launch (a hipGraph replay).
+
+    ``items``: iterable of ``(plan, erased, blocks, S)``; ``erased`` empty for
+    an encode; ``blocks`` holds k + m device buffers (entries that are neither
+    inputs nor outputs may be None).
+    """
+
+    def __init__(self, items, tile_bytes: int = 0, grid: int = 0, wg_threads: int = 0,
+                 static_queue: bool = False):
+        from ._lib import BatchItem, Tune
+        items = list(items)
+        self._keep = []
+        arr = (BatchItem * max(1, len(items)))()
+        for i, (plan, erased, blocks, S) in enumerate(items):
+            if len(blocks) != plan.k + plan.m:
+                raise ValueError("each item needs k + m block entries")
+            er = (ctypes.c_int * max(1, len(erased)))(*erased)
+            bl = _ptr_array(blocks)
+            self._keep += [er, bl, plan]
+            arr[i].plan = plan._h
+            arr[i].n_erased = len(erased)
+            arr[i].erased = ctypes.cast(er, ctypes.POINTER(ctypes.c_int))
+            arr[i].blocks = ctypes.cast(bl, ctypes.POINTER(ctypes.c_void_p))
+            arr[i].slice_bytes = S
+        tune = Tune(tile_bytes, grid, wg_threads, 1 if static_queue else 0)
+        h = ctypes.c_void_p()
+        _check(lib().pyrit_batch_create(arr, len(items), ctypes.byref(tune), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None) -> None:
+        _check(lib().pyrit_batch_launch(self._h, _stream_handle(stream)))
+
+    def launch_direct(self, stream=None) -> None:
+        _check(lib().pyrit_batch_launch_direct(self._h, _stream_handle(stream)))
+
+    def info(self) -> dict:
+        np_, ni, gr, wg = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        mv = ctypes.c_uint64()
+        _check(lib().pyrit_batch_info(self._h, ctypes.byref(np_), ctypes.byref(ni),
+                                      ctypes.byref(mv), ctypes.byref(gr), ctypes.byref(wg)))
+        return {"passes": np_.value, "work_items": ni.value, "moved_bytes": mv.value,
+                "grid": gr.value, "wg_threads": wg.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pyrit_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def fill_random(buf, key: int, nrandom: int | None = None, nbytes: int | None = None,

@@ -40,7 +40,24 @@ SIGNATURES = {
     "pyrit_decode": (c_int, [c_vp, c_vp, c_int, c_vp, c_size, c_vp]),
     "pyrit_fill_random": (c_int, [c_vp, c_size, c_size, c_u64, c_vp]),
     "pyrit_copy": (c_int, [c_vp, c_vp, c_size, c_vp]),
+    "pyrit_batch_create": (c_int, [c_vp, c_int, c_vp, P(c_vp)]),
+    "pyrit_batch_launch": (c_int, [c_vp, c_vp]),
+    "pyrit_batch_launch_direct": (c_int, [c_vp, c_vp]),
+    "pyrit_batch_info": (c_int, [c_vp, P(c_int), P(c_int), P(c_u64), P(c_int), P(c_int)]),
+    "pyrit_batch_destroy": (None, [c_vp]),
 }
+
+
+class BatchItem(ctypes.Structure):
+    """pyrit_batch_item"""
+    _fields_ = [("plan", c_vp), ("n_erased", c_int), ("erased", P(c_int)),
+                ("blocks", P(c_vp)), ("slice_bytes", c_size)]
+
+
+class Tune(ctypes.Structure):
+    """pyrit_tune"""
+    _fields_ = [("tile_bytes", c_int), ("grid", c_int), ("wg_threads", c_int),
+                ("static_queue", c_int)]
 
 
 def lib():

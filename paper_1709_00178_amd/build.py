@@ -19,6 +19,7 @@ ARCH = "gfx950"
 SOURCES = [
     "plan.cpp",
     "device_api.hip",
+    "batch.hip",
     "plain_ring0.hip",
     "plain_ring1.hip",
     "plain_ring2.hip",

@@ -51,3 +51,37 @@ def oracle_cols(st, G, in_ids, cols, nthreads=4):
     f = oracle.Field(st.w, st.p)
     ins = [gen_cols(st, j, cols) for j in in_ids]
     return f.encode(np.ascontiguousarray(G, dtype=np.uint16), ins, len(cols), nthreads=nthreads)
+
+
+class Arena:
+    """One device allocation carved into 256-byte aligned block buffers."""
+
+    def __init__(self, nbytes):
+        self.buf = dev_empty(nbytes)
+        self.off = 0
+
+    def take(self, nbytes):
+        off = self.off
+        self.off = off + (nbytes + 255) // 256 * 256
+        assert self.off <= self.buf.numel(), "arena exhausted"
+        return self.buf[off:off + nbytes]
+
+
+def stripe_buffers(st, arena, fill=True):
+    """Device blocks of one stripe: inputs filled with the generator, outputs
+    allocated; returns (blocks list of k+m entries, input ids, output ids)."""
+    ins = list(W.survivors(st))
+    outs = list(st.erased) if st.erased else list(range(st.k, st.k + st.m))
+    blocks = [None] * (st.k + st.m)
+    for b in ins:
+        blocks[b] = arena.take(st.block_len)
+        if fill:
+            P.fill_random(blocks[b], st.key(b), nrandom=st.B)
+    for b in outs:
+        blocks[b] = arena.take(st.block_len)
+    return blocks, ins, outs
+
+
+def stripe_bytes_needed(st):
+    n_out = len(st.erased) if st.erased else st.m
+    return (st.k + n_out) * ((st.block_len + 255) // 256 * 256)

@@ -1,0 +1,185 @@
+"""Persistent batched kernel (one launch, hipGraph replay) against the CPU
+oracle, bit-exact, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1709_00178_amd as P
+from paper_1709_00178_amd import workloads as W
+from tests.gpu_util import (Arena, gather_cols, oracle_cols, sample_cols, stripe_buffers,
+                            stripe_bytes_needed, to_host, torch_mod)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    torch = torch_mod()
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    oracle.build()
+    yield
+    torch.cuda.synchronize()
+
+
+def sync():
+    torch_mod().cuda.synchronize()
+
+
+class PlanCache:
+    def __init__(self):
+        self.plans = {}
+
+    def get(self, st):
+        key = (st.w, st.n, st.p, st.k, st.m)
+        if key not in self.plans:
+            self.plans[key] = P.Plan(*key)
+        return self.plans[key]
+
+
+def _check_stripes(stripes, bufs, plans, ncols=16, seed=0):
+    """Sampled columns of every output of every stripe against the oracle
+    (columns gathered on the device, copied back, compared on the host)."""
+    torch = torch_mod()
+    for si, st in enumerate(stripes):
+        blocks, ins, outs = bufs[si]
+        plan = plans.get(st)
+        G = plan.decode_matrix(list(st.erased))[1] if st.erased else plan.G
+        cols = sample_cols(st.S, ncols, seed + st.stripe)
+        want = oracle_cols(st, G, ins, cols, nthreads=1)
+        idx = torch.as_tensor((np.arange(st.w)[:, None] * st.S + cols[None, :]).reshape(-1),
+                              device="cuda")
+        got_all = torch.stack([blocks[b][idx] for b in outs]).cpu().numpy()
+        for r, b in enumerate(outs):
+            assert np.array_equal(got_all[r], want[r]), (si, st, b)
+
+
+def _build(stripes, plans, arena):
+    bufs = [stripe_buffers(st, arena) for st in stripes]
+    items = [(plans.get(st), list(st.erased), bufs[i][0], st.S) for i, st in enumerate(stripes)]
+    return bufs, items
+
+
+def _clear_outputs(bufs, value):
+    for blocks, ins, outs in bufs:
+        for b in outs:
+            blocks[b].fill_(value)
+
+
+def test_batch_single_stripe_every_shape():
+    """C0 stripe in every launch shape: graph and direct launch, dynamic and
+    static queues, 64/128/256-thread workgroups, several tile widths."""
+    st = W.c0()
+    plans = PlanCache()
+    arena = Arena(stripe_bytes_needed(st) + 4096)
+    bufs, items = _build([st], plans, arena)
+    host = W.host_blocks(st)
+    want = oracle.Field(st.w, st.p).encode(plans.get(st).G, host, st.S, nthreads=4)
+    for wg in [64, 128, 256]:
+        for static in [False, True]:
+            for tile in [0, 512, 4096]:
+                b = P.Batch(items, tile_bytes=tile, wg_threads=wg, static_queue=static)
+                for launch in [b.launch, b.launch_direct]:
+                    _clear_outputs(bufs, 0xEE)
+                    launch()
+                    sync()
+                    for i in range(st.m):
+                        got = to_host(bufs[0][0][st.k + i])
+                        assert np.array_equal(got, want[i]), (wg, static, tile, i)
+                b.close()
+
+
+def test_batch_graph_replays_with_eager_work_between():
+    """Each replay recomputes every output; eager fills between replays."""
+    stripes = W.c2(8)
+    plans = PlanCache()
+    arena = Arena(sum(stripe_bytes_needed(s) for s in stripes) + 4096)
+    bufs, items = _build(stripes, plans, arena)
+    b = P.Batch(items)
+    for rep in range(4):
+        _clear_outputs(bufs, rep * 17)
+        b.launch()
+        sync()
+        _check_stripes(stripes, bufs, plans, ncols=8, seed=rep)
+
+
+def test_c2_all_stripes_one_launch():
+    stripes = W.c2()
+    plans = PlanCache()
+    arena = Arena(sum(stripe_bytes_needed(s) for s in stripes) + 4096)
+    bufs, items = _build(stripes, plans, arena)
+    b = P.Batch(items)
+    info = b.info()
+    assert info["passes"] == 256
+    assert info["moved_bytes"] == sum(s.moved_bytes() for s in stripes)
+    b.launch()
+    sync()
+    _check_stripes(stripes, bufs, plans, ncols=12)
+
+
+def test_c3_all_4096_uneven_stripes_one_launch():
+    """The uneven batch: w in {4,8,10}, k in [4,16], m in [2,4], 4 KiB..4 MiB
+    blocks, 30% decodes, all in one persistent launch."""
+    stripes = W.c3()
+    plans = PlanCache()
+    arena = Arena(sum(stripe_bytes_needed(s) for s in stripes) + 4096)
+    bufs, items = _build(stripes, plans, arena)
+    b = P.Batch(items)
+    info = b.info()
+    assert info["moved_bytes"] == sum(s.moved_bytes() for s in stripes)
+    _clear_outputs(bufs, 0x77)
+    b.launch()
+    sync()
+    _check_stripes(stripes, bufs, plans, ncols=10)
+
+
+def test_batch_matches_plain_kernel_bytes():
+    """Batched and plain outputs are identical for C1-shaped stripes with
+    6 outputs (two passes) and a decode."""
+    torch = torch_mod()
+    st = W.Stripe(8, 17, 0x139, k=10, m=6, B=8 * 64 * 1000, seed=21)
+    plan = P.Plan(st.w, st.n, st.p, st.k, st.m)
+    arena = Arena(3 * (st.k + st.m) * st.block_len + 8192)
+    data = [arena.take(st.block_len) for _ in range(st.k)]
+    for j, t in enumerate(data):
+        P.fill_random(t, st.key(j))
+    par_plain = [arena.take(st.block_len) for _ in range(st.m)]
+    par_batch = [arena.take(st.block_len) for _ in range(st.m)]
+    plan.encode(data, par_plain, st.S)
+    b = P.Batch([(plan, [], data + par_batch, st.S)])
+    b.launch()
+    sync()
+    for a, c in zip(par_plain, par_batch):
+        assert torch.equal(a, c)
+    # decode two data blocks and two parity blocks through the batch path
+    er = [1, 7, 11, 14]
+    blocks = data + par_plain
+    outs = {e: arena.take(st.block_len) for e in er}
+    bl = [outs.get(i, blocks[i]) for i in range(st.k + st.m)]
+    b2 = P.Batch([(plan, er, bl, st.S)])
+    b2.launch()
+    sync()
+    for e in er:
+        assert torch.equal(outs[e], blocks[e]), e
+
+
+def test_batch_errors():
+    st = W.c0()
+    plan = P.Plan(st.w, st.n, st.p, st.k, st.m)
+    arena = Arena(8 * st.block_len + 8192)
+    blocks = [arena.take(st.block_len) for _ in range(6)]
+    with pytest.raises(P.PyritError) as e:
+        P.Batch([(plan, [], [blocks[0].data_ptr() + 4] + blocks[1:], st.S)])
+    assert e.value.code == -8
+    with pytest.raises(P.PyritError) as e:
+        P.Batch([(plan, [0, 1, 2], blocks, st.S)])
+    assert e.value.code == -6
+    bad = P.Plan(3, 7, 0xB, 3, 2)
+    with pytest.raises(P.PyritError) as e:
+        P.Batch([(bad, [], blocks[:5], 64)])
+    assert e.value.code == -9
+    with pytest.raises(P.PyritError) as e:
+        P.Batch([(plan, [], blocks, st.S)], wg_threads=96)
+    assert e.value.code == -1
+    empty = P.Batch([])
+    empty.launch()
+    sync()
