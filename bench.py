@@ -75,15 +75,25 @@ def per_call_ms(fn, reps, stream):
     return ms[len(ms) // 2], ms[min(len(ms) - 1, int(round(0.99 * (len(ms) - 1))))]
 
 
+# Gap left between consecutive blocks in device memory, so that blocks do
+# not start at addresses congruent modulo large powers of two (which maps the
+# same column of every block onto the same HBM channel and bank).
+BLOCK_SKEW = 4352
+
+
 class Arena:
-    def __init__(self, nbytes):
+    """One device allocation carved into 256-byte aligned blocks, each
+    followed by `skew` unused bytes."""
+
+    def __init__(self, nbytes, skew=0):
         import torch
         self.buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         self.off = 0
+        self.skew = skew
 
     def take(self, nbytes):
         off = self.off
-        self.off = off + (nbytes + 255) // 256 * 256
+        self.off = off + (nbytes + 255) // 256 * 256 + self.skew
         assert self.off <= self.buf.numel()
         return self.buf[off:off + nbytes]
 
@@ -96,17 +106,17 @@ def stripe_buffers(st, arena):
     blocks = [None] * (st.k + st.m)
     for b in ins:
         blocks[b] = arena.take(st.block_len)
-        P.fill_random(blocks[b], st.key(b), nrandom=st.B)
+        P.fill_random(blocks[b], st.key(b), nrandom=st.nrandom)
     for b in outs:
         blocks[b] = arena.take(st.block_len)
     return blocks
 
 
-def arena_bytes(stripes):
+def arena_bytes(stripes, skew=0):
     tot = 0
     for st in stripes:
         n_out = len(st.erased) if st.erased else st.m
-        tot += (st.k + n_out) * ((st.block_len + 255) // 256 * 256)
+        tot += (st.k + n_out) * ((st.block_len + 255) // 256 * 256 + skew)
     return tot + 4096
 
 
@@ -137,79 +147,108 @@ def cpu_baseline(target_s: float = 10.0):
                       f"slice ({st.k * st.w * Sp / 1e6:.0f} MB of data) x {reps} passes, {el:.1f} s"}
 
 
-def bench_c1(args, stream, out):
+def c1_layout(args, stream, st, skew, log):
+    """Plain and batched encode of the C1 stripe in one memory layout."""
     import torch
 
     import paper_1709_00178_amd as P
-    from paper_1709_00178_amd import workloads as W
-    st = W.c1()
+    from paper_1709_00178_amd import autotune
     plan = P.Plan(st.w, st.n, st.p, st.k, st.m)
-    arena = Arena(arena_bytes([st]))
+    arena = Arena(arena_bytes([st], skew), skew)
     blocks = stripe_buffers(st, arena)
     data, par = blocks[:st.k], blocks[st.k:]
-    batch = P.Batch([(plan, [], blocks, st.S)])
+    items = [(plan, [], blocks, st.S, st.pitch)]
+    batch, cfg, tried = autotune.tuned_batch(items, stream, log=log)
     torch.cuda.synchronize()
 
     def enc_batched():
         batch.launch(stream)
 
     def enc_plain():
-        plan.encode(data, par, st.S, stream=stream)
+        plan.encode(data, par, st.S, stream=stream, pitch=st.pitch)
 
-    for _ in range(args.warmup):
+    reps = max(20, args.steps)
+    for _ in range(3):
         enc_batched()
+        enc_plain()
+    b_ms = batch_time_ms(enc_batched, reps, stream)
+    b_p50, b_p99 = per_call_ms(enc_batched, 20, stream)
+    p_ms = batch_time_ms(enc_plain, reps, stream)
+    p_p50, p_p99 = per_call_ms(enc_plain, 20, stream)
+    moved = st.moved_bytes()
+    res = {"layout": {"slice_pitch": st.pitch, "block_skew": skew},
+           "batched": {"executor": cfg,
+                       "GBps_data": round(st.k * st.B / (b_ms * 1e-3) / 1e9, 1),
+                       "GBps_moved": round(moved / (b_ms * 1e-3) / 1e9, 1),
+                       "frac_of_peak": round(moved / (b_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                       "avg_ms": round(b_ms, 4), "p50_ms": round(b_p50, 4),
+                       "p99_ms": round(b_p99, 4), "work_items": batch.info()["work_items"]},
+           "plain": {"GBps_data": round(st.k * st.B / (p_ms * 1e-3) / 1e9, 1),
+                     "GBps_moved": round(moved / (p_ms * 1e-3) / 1e9, 1),
+                     "frac_of_peak": round(moved / (p_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                     "avg_ms": round(p_ms, 4), "p50_ms": round(p_p50, 4),
+                     "p99_ms": round(p_p99, 4)}}
+    if tried:
+        res["batched"]["tuning_ms"] = {f"{c['mode']}/{c['wg_threads']}/{c.get('tile_bytes', 0)}":
+                                       round(ms, 4) for c, ms in tried}
+    return res, plan, blocks, batch, arena
+
+
+def bench_c1(args, stream, out, log):
+    import dataclasses
+
+    import torch
+
+    import paper_1709_00178_amd as P
+    from paper_1709_00178_amd import workloads as W
+    packed = W.c1()
+    padded = dataclasses.replace(packed, pad=4096)
+    res_packed, *_ = c1_layout(args, stream, packed, 0, log)
+    torch.cuda.empty_cache()
+    res, plan, blocks, batch, arena = c1_layout(args, stream, padded, BLOCK_SKEW, log)
+    st = padded
+
+    # the timed steps: batched encodes of the stripe, inputs resident in HBM
+    for _ in range(args.warmup):
+        batch.launch(stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        enc_batched()
+        batch.launch(stream)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-
-    moved = st.moved_bytes()
-    reps = max(20, args.steps)
-    b_ms = batch_time_ms(enc_batched, reps, stream)
-    b_p50, b_p99 = per_call_ms(enc_batched, 20, stream)
-    for _ in range(3):
-        enc_plain()
-    p_ms = batch_time_ms(enc_plain, reps, stream)
-    p_p50, p_p99 = per_call_ms(enc_plain, 20, stream)
 
     # decode of the workload's random 4-erasure pattern: the stripe is a valid
     # codeword, so the erased blocks are rewritten with the bytes they hold
     er = list(W.c1_erasure_patterns()[0])
-    dbatch = P.Batch([(plan, er, blocks, st.S)])
+    dbatch = P.Batch([(plan, er, blocks, st.S, st.pitch)], **res["batched"]["executor"])
     for _ in range(3):
-        plan.decode(er, blocks, st.S, stream=stream)
+        plan.decode(er, blocks, st.S, stream=stream, pitch=st.pitch)
         dbatch.launch(stream)
-    d_plain = batch_time_ms(lambda: plan.decode(er, blocks, st.S, stream=stream), 20, stream)
+    d_plain = batch_time_ms(lambda: plan.decode(er, blocks, st.S, stream=stream, pitch=st.pitch),
+                            20, stream)
     d_batch = batch_time_ms(lambda: dbatch.launch(stream), 20, stream)
-    d_moved = (st.k + len(er)) * st.block_len
+    d_moved = (st.k + len(er)) * st.data_len
 
-    info = batch.info()
+    moved = st.moved_bytes()
+    b_ms = res["batched"]["avg_ms"]
     achieved = moved / (b_ms * 1e-3) / 1e9
+    kname = {"grid": "batch_grid_kernel", "queue": "batch_persistent_kernel<queue>",
+             "static": "batch_persistent_kernel<static>"}[res["batched"]["executor"]["mode"]]
     out.update({
         "value": round(st.k * st.B * args.steps / el / 1e9, 2),
         "ms_per_step": round(el * 1e3 / args.steps, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                      "traffic": traffic_record("batch_c1"),
-                     "kernel": "pyrit::batch_kernel<256>",
+                     "kernel": f"pyrit::{kname}<{res['batched']['executor']['wg_threads']}>",
                      "algorithmic_bytes_per_launch": moved,
-                     "avg_launch_ms": round(b_ms, 4)},
-        "c1": {
-            "batched": {"GBps_data": round(st.k * st.B / (b_ms * 1e-3) / 1e9, 1),
-                        "GBps_moved": round(achieved, 1), "avg_ms": round(b_ms, 4),
-                        "p50_ms": round(b_p50, 4), "p99_ms": round(b_p99, 4),
-                        "grid": info["grid"], "work_items": info["work_items"]},
-            "plain": {"GBps_data": round(st.k * st.B / (p_ms * 1e-3) / 1e9, 1),
-                      "GBps_moved": round(moved / (p_ms * 1e-3) / 1e9, 1),
-                      "avg_ms": round(p_ms, 4), "p50_ms": round(p_p50, 4),
-                      "p99_ms": round(p_p99, 4)},
-            "decode_4_erasures": {"erased": er,
-                                  "plain_GBps_moved": round(d_moved / (d_plain * 1e-3) / 1e9, 1),
-                                  "batched_GBps_moved": round(d_moved / (d_batch * 1e-3) / 1e9, 1),
-                                  "plain_ms": round(d_plain, 4), "batched_ms": round(d_batch, 4)},
-        },
+                     "avg_launch_ms": b_ms},
+        "c1": {"padded_layout": res, "packed_layout": res_packed,
+               "decode_4_erasures": {"erased": er,
+                                     "plain_GBps_moved": round(d_moved / (d_plain * 1e-3) / 1e9, 1),
+                                     "batched_GBps_moved": round(d_moved / (d_batch * 1e-3) / 1e9, 1),
+                                     "plain_ms": round(d_plain, 4), "batched_ms": round(d_batch, 4)}},
     })
     # device copy of the same byte volume: a bandwidth reference
     half = (moved // 2) // 16 * 16
@@ -218,21 +257,23 @@ def bench_c1(args, stream, out):
     P.copy(dst, src, stream=stream)
     cp_ms = batch_time_ms(lambda: P.copy(dst, src, stream=stream), 20, stream)
     out["copy_ceiling_GBps"] = round(2 * half / (cp_ms * 1e-3) / 1e9, 1)
-    del batch, dbatch, arena
+    del batch, dbatch, arena, blocks
     torch.cuda.empty_cache()
 
 
-def bench_c2(args, stream, out):
+def bench_c2(args, stream, out, log):
     import torch
 
     import paper_1709_00178_amd as P
+    from paper_1709_00178_amd import autotune
     from paper_1709_00178_amd import workloads as W
     stripes = W.c2()
     st0 = stripes[0]
     plan = P.Plan(st0.w, st0.n, st0.p, st0.k, st0.m)
-    arena = Arena(arena_bytes(stripes))
+    arena = Arena(arena_bytes(stripes, BLOCK_SKEW), BLOCK_SKEW)
     bl = [stripe_buffers(st, arena) for st in stripes]
-    batch = P.Batch([(plan, [], b, st.S) for st, b in zip(stripes, bl)])
+    batch, cfg, _ = autotune.tuned_batch([(plan, [], b, st.S) for st, b in zip(stripes, bl)],
+                                         stream, log=log)
     torch.cuda.synchronize()
 
     def plain_all():
@@ -253,15 +294,17 @@ def bench_c2(args, stream, out):
                                       "GBps_data": round(user / (b_ms * 1e-3) / 1e9, 1),
                                       "GBps_moved": round(moved / (b_ms * 1e-3) / 1e9, 1),
                                       "frac_of_peak": round(moved / (b_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                                      "executor": cfg,
                                       "work_items": batch.info()["work_items"]}}
     del batch, arena, bl
     torch.cuda.empty_cache()
 
 
-def bench_c3(args, stream, out):
+def bench_c3(args, stream, out, log):
     import torch
 
     import paper_1709_00178_amd as P
+    from paper_1709_00178_amd import autotune
     from paper_1709_00178_amd import workloads as W
     stripes = W.c3()
     plans = {}
@@ -269,11 +312,13 @@ def bench_c3(args, stream, out):
         key = (st.w, st.n, st.p, st.k, st.m)
         if key not in plans:
             plans[key] = P.Plan(*key)
-    arena = Arena(arena_bytes(stripes))
+    arena = Arena(arena_bytes(stripes, BLOCK_SKEW), BLOCK_SKEW)
     bl = [stripe_buffers(st, arena) for st in stripes]
+    items = [(plans[(st.w, st.n, st.p, st.k, st.m)], list(st.erased), b, st.S)
+             for st, b in zip(stripes, bl)]
+    batch, cfg, _ = autotune.tuned_batch(items, stream, log=log)
     t0 = time.perf_counter()
-    batch = P.Batch([(plans[(st.w, st.n, st.p, st.k, st.m)], list(st.erased), b, st.S)
-                     for st, b in zip(stripes, bl)])
+    P.Batch(items, **cfg).close()
     build_s = time.perf_counter() - t0
     torch.cuda.synchronize()
     batch.launch(stream)
@@ -283,7 +328,8 @@ def bench_c3(args, stream, out):
                  "moved_GB": round(moved / 1e9, 3), "ms": round(b_ms, 3),
                  "GBps_moved": round(moved / (b_ms * 1e-3) / 1e9, 1),
                  "frac_of_peak": round(moved / (b_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
-                 "batch_build_s": round(build_s, 3), "work_items": batch.info()["work_items"]}
+                 "batch_build_s": round(build_s, 3), "executor": cfg,
+                 "work_items": batch.info()["work_items"]}
     del batch, arena, bl
     torch.cuda.empty_cache()
 
@@ -308,23 +354,29 @@ def main():
     from paper_1709_00178_amd import workloads as W
     st = W.c1()
     out = {
-        "metric": "encode GB/s of data (GF(2^8) k=10 m=4, 64 MiB blocks), batched persistent kernel",
+        "metric": "encode GB/s of data (GF(2^8) k=10 m=4, 64 MiB blocks), batched launch",
         "value": None, "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u8", "data": "synthetic (seeded SplitMix64 bytes generated in HBM)",
         "config": {"workload": "GF(2^8) in R_{2,17}, p = x^8+x^5+x^4+x^3+1, Cauchy k=10 m=4, one "
-                               "stripe of 64 MiB blocks (8 slices of 8 MiB), batched persistent "
-                               "kernel replayed as a hipGraph",
+                               "stripe of 64 MiB blocks (8 slices of 8 MiB at an 8 MiB + 4 KiB "
+                               "pitch, blocks 4352 B apart), batched executor replayed as a "
+                               "hipGraph",
                    "k": st.k, "m": st.m, "w": st.w, "n": st.n, "block_bytes": st.B,
-                   "slice_bytes": st.S, "parallelism": "1 GPU"},
+                   "slice_bytes": st.S, "slice_pitch": st.S + 4096, "block_skew": BLOCK_SKEW,
+                   "parallelism": "1 GPU"},
     }
     only = set(args.only.split(","))
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
     if "c1" in only:
-        bench_c1(args, stream, out)
+        bench_c1(args, stream, out, log)
     if "c2" in only:
-        bench_c2(args, stream, out)
+        bench_c2(args, stream, out, log)
     if "c3" in only:
-        bench_c3(args, stream, out)
+        bench_c3(args, stream, out, log)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -154,35 +154,42 @@ class Plan:
                                          D.ctypes.data))
         return surv, D
 
-    def encode(self, data, parity, S: int, stream=None, vec_bytes: int = 0) -> None:
+    def encode(self, data, parity, S: int, stream=None, vec_bytes: int = 0,
+               pitch: int = 0) -> None:
+        """parity[i] = sum_j G[i][j] * data[j]; blocks are w slices of S bytes
+        at a stride of ``pitch`` bytes (0: packed, pitch = S)."""
         if len(data) != self.k or len(parity) != self.m:
             raise ValueError("need k data and m parity buffers")
-        _check(lib().pyrit_encode_vec(self._h, _ptr_array(data), _ptr_array(parity), S,
-                                      vec_bytes, _stream_handle(stream)))
+        _check(lib().pyrit_encode_ex(self._h, _ptr_array(data), _ptr_array(parity), S, pitch,
+                                     vec_bytes, _stream_handle(stream)))
 
-    def decode(self, erased, blocks, S: int, stream=None) -> None:
+    def decode(self, erased, blocks, S: int, stream=None, pitch: int = 0) -> None:
+        """Rewrite the erased entries of ``blocks`` (k + m buffers)."""
         if len(blocks) != self.k + self.m:
             raise ValueError("need k + m block buffers")
         er = (ctypes.c_int * max(1, len(erased)))(*erased)
-        _check(lib().pyrit_decode(self._h, er, len(erased), _ptr_array(blocks), S,
-                                  _stream_handle(stream)))
+        _check(lib().pyrit_decode_ex(self._h, er, len(erased), _ptr_array(blocks), S, pitch,
+                                     _stream_handle(stream)))
 
 
 class Batch:
     """Many stripes coded by one persistent-kernel launch (a hipGraph replay).
 
-    ``items``: iterable of ``(plan, erased, blocks, S)``; ``erased`` empty for
-    an encode; ``blocks`` holds k + m device buffers (entries that are neither
-    inputs nor outputs may be None).
+    ``items``: iterable of ``(plan, erased, blocks, S)`` or ``(plan, erased,
+    blocks, S, pitch)``; ``erased`` empty for an encode; ``blocks`` holds
+    k + m device buffers (entries that are neither inputs nor outputs may be
+    None).
     """
 
-    def __init__(self, items, tile_bytes: int = 0, grid: int = 0, wg_threads: int = 0,
-                 static_queue: bool = False):
-        from ._lib import BatchItem, Tune
+    def __init__(self, items, mode: str = "grid", tile_bytes: int = 0, grid: int = 0,
+                 wg_threads: int = 0):
+        from ._lib import BATCH_MODES, BatchItem, Tune
         items = list(items)
         self._keep = []
         arr = (BatchItem * max(1, len(items)))()
-        for i, (plan, erased, blocks, S) in enumerate(items):
+        for i, it in enumerate(items):
+            plan, erased, blocks, S = it[:4]
+            pitch = it[4] if len(it) > 4 else 0
             if len(blocks) != plan.k + plan.m:
                 raise ValueError("each item needs k + m block entries")
             er = (ctypes.c_int * max(1, len(erased)))(*erased)
@@ -193,7 +200,11 @@ class Batch:
             arr[i].erased = ctypes.cast(er, ctypes.POINTER(ctypes.c_int))
             arr[i].blocks = ctypes.cast(bl, ctypes.POINTER(ctypes.c_void_p))
             arr[i].slice_bytes = S
-        tune = Tune(tile_bytes, grid, wg_threads, 1 if static_queue else 0)
+            arr[i].slice_pitch = pitch
+        if mode not in BATCH_MODES:
+            raise ValueError(f"mode must be one of {sorted(BATCH_MODES)}")
+        self.mode = mode
+        tune = Tune(BATCH_MODES[mode], tile_bytes, grid, wg_threads)
         h = ctypes.c_void_p()
         _check(lib().pyrit_batch_create(arr, len(items), ctypes.byref(tune), ctypes.byref(h)))
         self._h = h

@@ -36,7 +36,8 @@ SIGNATURES = {
     "pyrit_plan_weight": (c_int, [c_vp, P(c_int)]),
     "pyrit_decode_matrix": (c_int, [c_vp, c_vp, c_int, c_vp, c_vp]),
     "pyrit_encode": (c_int, [c_vp, c_vp, c_vp, c_size, c_vp]),
-    "pyrit_encode_vec": (c_int, [c_vp, c_vp, c_vp, c_size, c_int, c_vp]),
+    "pyrit_encode_ex": (c_int, [c_vp, c_vp, c_vp, c_size, c_size, c_int, c_vp]),
+    "pyrit_decode_ex": (c_int, [c_vp, c_vp, c_int, c_vp, c_size, c_size, c_vp]),
     "pyrit_decode": (c_int, [c_vp, c_vp, c_int, c_vp, c_size, c_vp]),
     "pyrit_fill_random": (c_int, [c_vp, c_size, c_size, c_u64, c_vp]),
     "pyrit_copy": (c_int, [c_vp, c_vp, c_size, c_vp]),
@@ -51,13 +52,16 @@ SIGNATURES = {
 class BatchItem(ctypes.Structure):
     """pyrit_batch_item"""
     _fields_ = [("plan", c_vp), ("n_erased", c_int), ("erased", P(c_int)),
-                ("blocks", P(c_vp)), ("slice_bytes", c_size)]
+                ("blocks", P(c_vp)), ("slice_bytes", c_size), ("slice_pitch", c_size)]
 
 
 class Tune(ctypes.Structure):
     """pyrit_tune"""
-    _fields_ = [("tile_bytes", c_int), ("grid", c_int), ("wg_threads", c_int),
-                ("static_queue", c_int)]
+    _fields_ = [("mode", c_int), ("tile_bytes", c_int), ("grid", c_int),
+                ("wg_threads", c_int)]
+
+
+BATCH_MODES = {"grid": 0, "queue": 1, "static": 2}
 
 
 def lib():

@@ -1,0 +1,125 @@
+"""Autotuner for batched launches.
+
+For a batch it times a small set of executors (queue drain mode, threads per
+workgroup, tile width) with HIP events on the caller's stream and keeps the
+fastest.  Results are cached per batch signature (rings, code shapes, slice
+size class, encode/decode mix) in memory and in a JSON file
+(``PYRIT_AUTOTUNE_CACHE``, default ``~/.cache/pyrit_mi355x_autotune.json``),
+so a signature is only tuned once per machine.
+
+Timing launches the batch itself, so tuning writes the batch's outputs (with
+the bytes a real launch writes).
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import threading
+
+from . import Batch
+
+CANDIDATES = [
+    {"mode": "grid", "wg_threads": 64},
+    {"mode": "grid", "wg_threads": 128},
+    {"mode": "grid", "wg_threads": 256},
+    {"mode": "queue", "wg_threads": 256, "tile_bytes": 0},
+    {"mode": "queue", "wg_threads": 256, "tile_bytes": 4096},
+    {"mode": "static", "wg_threads": 128, "tile_bytes": 0},
+]
+
+_lock = threading.Lock()
+_mem: dict = {}
+
+
+def cache_path() -> str:
+    return os.environ.get("PYRIT_AUTOTUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache",
+                                       "pyrit_mi355x_autotune.json"))
+
+
+def _load_file() -> dict:
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save_file(d: dict) -> None:
+    path = cache_path()
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(d, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass  # a read-only home only loses persistence
+
+
+def signature(items) -> str:
+    """Batch class: rings present, k/outputs ranges, log2 slice size range,
+    decode share and stripe-count class."""
+    rings, ks, outs, sizes, dec = set(), [], [], [], 0
+    for it in items:
+        plan, erased, _, S = it[:4]
+        rings.add((plan.w, plan.n, plan.p))
+        ks.append(plan.k)
+        outs.append(len(erased) if erased else plan.m)
+        sizes.append(S)
+        dec += 1 if erased else 0
+    n = len(ks)
+    if n == 0:
+        return "empty"
+    return "|".join([
+        ",".join(f"{w}/{nn}/{p:x}" for w, nn, p in sorted(rings)),
+        f"k{min(ks)}-{max(ks)}", f"o{min(outs)}-{max(outs)}",
+        f"s{int(math.log2(min(sizes)))}-{int(math.log2(max(sizes)))}",
+        f"d{round(10 * dec / n)}", f"n{int(math.log2(n))}",
+    ])
+
+
+def time_batch(batch, stream, reps: int = 5) -> float:
+    import torch
+    batch.launch(stream)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        batch.launch(stream)
+    b.record(stream)
+    b.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def tuned_batch(items, stream=None, candidates=None, retune: bool = False, log=None):
+    """A Batch of `items` built with the fastest known executor for their
+    signature (tuning it now if unknown).  Returns (batch, config, timings)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    items = list(items)
+    sig = signature(items)
+    with _lock:
+        if not _mem:
+            _mem.update(_load_file())
+        cfg = None if retune else _mem.get(sig)
+    if cfg is not None:
+        return Batch(items, **cfg), cfg, None
+    timings = []
+    best, best_ms = None, float("inf")
+    for cand in candidates or CANDIDATES:
+        b = Batch(items, **cand)
+        ms = time_batch(b, stream)
+        timings.append((dict(cand), ms))
+        if log:
+            log(f"autotune {sig}: {cand} {ms:.4f} ms")
+        if ms < best_ms:
+            best, best_ms = cand, ms
+        b.close()
+    with _lock:
+        _mem[sig] = dict(best)
+        disk = _load_file()
+        disk[sig] = dict(best)
+        _save_file(disk)
+    return Batch(items, **best), dict(best), timings

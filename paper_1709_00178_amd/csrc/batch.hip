@@ -1,11 +1,23 @@
-// Batched form: one persistent kernel drains a queue of (pass, column-tile)
-// work items covering many stripes of any supported ring, and the launch is
-// captured once in a hipGraph.
+// Batched form: one launch codes a queue of (pass, column-tile) work items
+// covering many stripes of any supported ring; the launch is a hipGraph.
+//
+// Three ways to drain the queue (pyrit_tune.mode):
+//   grid   - one workgroup per item; the hardware dispatcher hands items to
+//            CUs in queue order as slots free up.
+//   queue  - persistent: a resident grid; each wave codes one item from a
+//            static slot, then claims items from one of eight atomic
+//            sub-queues (one per group of workgroups, so claims spread over
+//            eight counters).  Every launch makes a known number of claims
+//            per sub-queue, so the counters never need resetting: a claim's
+//            position in the current launch is its value modulo that number.
+//   static - persistent: the host assigns items to waves, longest first onto
+//            the least-loaded wave; waves walk their own lists.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstring>
 #include <memory>
+#include <queue>
 #include <vector>
 
 #include "internal.hpp"
@@ -18,29 +30,38 @@ namespace pyrit {
 // loads.
 #define AS4 __attribute__((address_space(4)))
 
+constexpr int kGroups = 8;  // sub-queues (one per XCD-sized group of workgroups)
+
 struct PassDesc {
   uint64_t in_tab;    // k input block pointers
   uint64_t out_tab;   // nout output block pointers
   uint64_t lift_tab;  // k x kMaxOut lifted coefficients (row j, column r)
   uint32_t k, nout, S, ring;
+  uint32_t pitch, pad;  // slice stride
 };
 
 struct WorkItem {
   uint32_t pass, col0, col1, ring;
 };
 
+enum : uint32_t { kModeGrid = 0, kModeQueue = 1, kModeStatic = 2 };
+
 struct BatchArgs {
   const PassDesc *passes;
   const WorkItem *items;
-  uint32_t *counters;  // [0] next item, [1] waves finished
+  const uint32_t *starts;  // queue: kGroups+1 sub-queue offsets; static: waves+1 list offsets
+  uint64_t *counters;      // queue: kGroups claim counters, 64 bytes apart
   uint32_t n_items;
   uint32_t total_waves;
-  uint32_t dynamic;
+  uint32_t n_passes;
 };
 
-// Lane width per ring inside the batch kernel: the widest that keeps every
-// ring at or below the (8,17) ring's register count (85 VGPRs at 4 outputs).
+// Lane width per ring inside the batch kernels: the widest that keeps every
+// ring at or below the (8,17) ring's register count (about 90 VGPRs with four
+// outputs), so one kernel holds all rings at five waves per SIMD.
 constexpr int kBatchV[kNumRings] = {2, 1, 1, 1, 1};
+
+__host__ __device__ constexpr uint32_t chunk_bytes(int ring) { return 64u * 4u * kBatchV[ring]; }
 
 struct TableSrc {
   const AS4 uint64_t *in_tab;
@@ -48,75 +69,150 @@ struct TableSrc {
   const AS4 uint32_t *lift_tab;
   int k_;
   uint32_t S_;
+  uint32_t pitch_;
   int nout_;
   __device__ int k() const { return k_; }
   __device__ uint32_t S() const { return S_; }
+  __device__ uint32_t pitch() const { return pitch_; }
   __device__ int nout() const { return nout_; }
   __device__ const uint8_t *in(int j) const { return (const uint8_t *)in_tab[j]; }
   __device__ uint8_t *out(int r) const { return (uint8_t *)out_tab[r]; }
   __device__ uint32_t lift(int j, int r) const { return lift_tab[j * kMaxOut + r]; }
 };
 
+__device__ __forceinline__ TableSrc table_src(const AS4 PassDesc *pd) {
+  return TableSrc{(const AS4 uint64_t *)pd->in_tab, (const AS4 uint64_t *)pd->out_tab,
+                  (const AS4 uint32_t *)pd->lift_tab, (int)pd->k, pd->S, pd->pitch, (int)pd->nout};
+}
+
 template <int RING>
-__device__ __forceinline__ void run_item(const AS4 PassDesc *pd, uint32_t col0, uint32_t col1,
+__device__ __forceinline__ void run_tile(const AS4 PassDesc *pd, uint32_t col0, uint32_t col1,
                                          uint32_t lane) {
   constexpr RingDesc R = kRings[RING];
+  dev::code_tile<R.w, R.n, R.p, kMaxOut, kBatchV[RING]>(table_src(pd), col0, col1, lane);
+}
+
+template <int RING>
+__device__ __forceinline__ void run_chunk(const AS4 PassDesc *pd, uint32_t base, uint32_t lane) {
+  constexpr RingDesc R = kRings[RING];
   constexpr int V = kBatchV[RING];
-  const TableSrc src{(const AS4 uint64_t *)pd->in_tab, (const AS4 uint64_t *)pd->out_tab,
-                     (const AS4 uint32_t *)pd->lift_tab, (int)pd->k, pd->S, (int)pd->nout};
-  for (uint32_t c = col0; c < col1; c += 64u * 4u * V) {
-    const uint32_t col = c + lane * 4u * V;
-    dev::code_column<R.w, R.n, R.p, kMaxOut, V>(src, col, col < src.S());
+  const TableSrc src = table_src(pd);
+  const uint32_t col = base + lane * 4u * V;
+  dev::code_column<R.w, R.n, R.p, kMaxOut, V>(src, col, col < src.S());
+}
+
+__device__ __forceinline__ void code_item(const AS4 PassDesc *passes, const AS4 WorkItem *it,
+                                          uint32_t lane) {
+  const AS4 PassDesc *pd = passes + it->pass;
+  const uint32_t c0 = it->col0, c1 = it->col1;
+  switch (it->ring) {
+    case 0: run_tile<0>(pd, c0, c1, lane); break;
+    case 1: run_tile<1>(pd, c0, c1, lane); break;
+    case 2: run_tile<2>(pd, c0, c1, lane); break;
+    case 3: run_tile<3>(pd, c0, c1, lane); break;
+    case 4: run_tile<4>(pd, c0, c1, lane); break;
+    default: break;
   }
 }
 
-__device__ __forceinline__ uint32_t queue_fetch(uint32_t *counter, uint32_t lane) {
-  uint32_t v = 0;
-  if (lane == 0) v = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// grid mode: workgroup b codes item b, one chunk per wave.  Items are
+// numbered pass by pass, so the workgroup finds its pass by binary search
+// over the per-pass start indices (a small array every workgroup reads, hot
+// in the scalar cache) instead of loading a per-item record.
+template <int WG>
+__global__ __launch_bounds__(WG) void batch_grid_kernel(const BatchArgs a) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const AS4 uint32_t *starts = (const AS4 uint32_t *)a.starts;
+  const uint32_t b = blockIdx.x;
+  uint32_t lo = 0, hi = a.n_passes;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (starts[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  const AS4 PassDesc *pd = (const AS4 PassDesc *)a.passes + lo;
+  const uint32_t ring = pd->ring;
+  const uint32_t chunk = chunk_bytes(ring);
+  const uint32_t base = ((b - starts[lo]) * (WG / 64) + wave) * chunk;
+  if (base >= pd->S) return;
+  switch (ring) {
+    case 0: run_chunk<0>(pd, base, lane); break;
+    case 1: run_chunk<1>(pd, base, lane); break;
+    case 2: run_chunk<2>(pd, base, lane); break;
+    case 3: run_chunk<3>(pd, base, lane); break;
+    case 4: run_chunk<4>(pd, base, lane); break;
+    default: break;
+  }
+}
+
+__device__ __forceinline__ uint64_t claim(uint64_t *counter, uint32_t lane) {
+  uint64_t v = 0;
+  if (lane == 0) v = __hip_atomic_fetch_add(counter, (uint64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return v;
 }
 
-template <int WG>
-__global__ __launch_bounds__(WG) void batch_kernel(const BatchArgs a) {
+__device__ __forceinline__ uint64_t first_lane64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+template <int WG, uint32_t MODE>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(5))) void batch_persistent_kernel(const BatchArgs a) {
+  constexpr uint32_t wpw = WG / 64;  // waves per workgroup
   const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t wave_id = __builtin_amdgcn_readfirstlane(blockIdx.x * (WG / 64) + (threadIdx.x >> 6));
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const AS4 WorkItem *items = (const AS4 WorkItem *)a.items;
   const AS4 PassDesc *passes = (const AS4 PassDesc *)a.passes;
-  uint32_t item = a.dynamic ? __builtin_amdgcn_readfirstlane(queue_fetch(a.counters, lane)) : wave_id;
-  while (item < a.n_items) {
-    // Claim the next item before coding this one; the claim completes while
-    // this item's first loads are in flight.
-    const uint32_t next_v = a.dynamic ? queue_fetch(a.counters, lane) : 0u;
-    const AS4 WorkItem *it = items + item;
-    const AS4 PassDesc *pd = passes + it->pass;
-    switch (it->ring) {
-      case 0: run_item<0>(pd, it->col0, it->col1, lane); break;
-      case 1: run_item<1>(pd, it->col0, it->col1, lane); break;
-      case 2: run_item<2>(pd, it->col0, it->col1, lane); break;
-      case 3: run_item<3>(pd, it->col0, it->col1, lane); break;
-      case 4: run_item<4>(pd, it->col0, it->col1, lane); break;
-      default: break;
-    }
-    item = a.dynamic ? __builtin_amdgcn_readfirstlane(next_v) : item + a.total_waves;
-  }
-  if (a.dynamic && lane == 0) {
-    // The last wave to finish rewinds the queue for the next launch.
-    const uint32_t done =
-        __hip_atomic_fetch_add(&a.counters[1], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (done == a.total_waves - 1) {
-      __hip_atomic_store(&a.counters[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&a.counters[1], 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  const AS4 uint32_t *starts = (const AS4 uint32_t *)a.starts;
+  if constexpr (MODE == kModeStatic) {
+    const uint32_t w = blockIdx.x * wpw + wave;
+    const uint32_t e = starts[w + 1];
+    for (uint32_t i = starts[w]; i < e; ++i) code_item(passes, items + i, lane);
+  } else {
+    const uint32_t g = blockIdx.x % kGroups;
+    const uint32_t l = (blockIdx.x / kGroups) * wpw + wave;       // wave within its group
+    const uint32_t wg_in_g = (gridDim.x - g + kGroups - 1) / kGroups;
+    const uint32_t W_g = wg_in_g * wpw;                            // waves in the group
+    const uint32_t q0 = starts[g], n_g = starts[g + 1] - q0;
+    const uint32_t dyn = n_g > W_g ? n_g - W_g : 0u;               // items claimed dynamically
+    const uint64_t C_g = (uint64_t)dyn + W_g;                      // claims per launch
+    uint64_t *ctr = a.counters + g * 8;
+    if (l < n_g) code_item(passes, items + q0 + l, lane);
+    // Claims are made between items (holding a claim in flight across an
+    // item would cost the registers of a sixth wave per SIMD).
+    while (true) {
+      const uint64_t pos = first_lane64(claim(ctr, lane)) % C_g;
+      if (pos >= dyn) break;
+      code_item(passes, items + q0 + W_g + (uint32_t)pos, lane);
     }
   }
 }
 
-static const void *batch_kernel_fn(int wg) {
+static const void *grid_fn(int wg) {
   switch (wg) {
-    case 64: return (const void *)batch_kernel<64>;
-    case 128: return (const void *)batch_kernel<128>;
-    case 256: return (const void *)batch_kernel<256>;
+    case 64: return (const void *)batch_grid_kernel<64>;
+    case 128: return (const void *)batch_grid_kernel<128>;
+    case 256: return (const void *)batch_grid_kernel<256>;
     default: return nullptr;
   }
+}
+
+static const void *persistent_fn(int wg, int mode) {
+  if (mode == kModeQueue) switch (wg) {
+      case 64: return (const void *)batch_persistent_kernel<64, kModeQueue>;
+      case 128: return (const void *)batch_persistent_kernel<128, kModeQueue>;
+      case 256: return (const void *)batch_persistent_kernel<256, kModeQueue>;
+      default: return nullptr;
+    }
+  if (mode == kModeStatic) switch (wg) {
+      case 64: return (const void *)batch_persistent_kernel<64, kModeStatic>;
+      case 128: return (const void *)batch_persistent_kernel<128, kModeStatic>;
+      case 256: return (const void *)batch_persistent_kernel<256, kModeStatic>;
+      default: return nullptr;
+    }
+  return nullptr;
 }
 
 }  // namespace pyrit
@@ -126,7 +222,9 @@ using namespace pyrit;
 struct pyrit_batch {
   void *dmem = nullptr;
   BatchArgs args{};
-  int grid = 0, wg = 256;
+  const void *fn = nullptr;
+  int mode = 0;
+  int grid = 0, wg = 128;
   int n_passes = 0;
   uint64_t moved = 0;
   hipGraph_t graph = nullptr;
@@ -143,7 +241,7 @@ namespace {
 struct HostPass {
   std::vector<uint64_t> in, out;
   std::vector<uint32_t> lift;  // k x kMaxOut
-  uint32_t k, nout, S;
+  uint32_t k, nout, S, pitch, w;
   int ring;
 };
 
@@ -154,7 +252,8 @@ int item_passes(const pyrit_batch_item &it, std::vector<HostPass> *out, uint64_t
   const pyrit_plan *pl = it.plan;
   if (!pl || !it.blocks) return PYRIT_EINVAL;
   if (pl->ring < 0) return PYRIT_EUNSUPPORTED;
-  int rc = check_slices(pl->w, it.slice_bytes);
+  size_t pitch = it.slice_pitch;
+  int rc = check_slices(pl->w, it.slice_bytes, &pitch);
   if (rc) return rc;
   std::vector<int> ins, outs;
   const uint32_t *L = nullptr;
@@ -170,17 +269,21 @@ int item_passes(const pyrit_batch_item &it, std::vector<HostPass> *out, uint64_t
     outs = ent->outs;
     L = ent->L.data();
   }
-  for (int b : ins)
+  for (int b : ins) {
     if (!it.blocks[b]) return PYRIT_EINVAL;
-    else if ((uintptr_t)it.blocks[b] & 15u) return PYRIT_EALIGN;
-  for (int b : outs)
+    if ((uintptr_t)it.blocks[b] & 15u) return PYRIT_EALIGN;
+  }
+  for (int b : outs) {
     if (!it.blocks[b]) return PYRIT_EINVAL;
-    else if ((uintptr_t)it.blocks[b] & 15u) return PYRIT_EALIGN;
+    if ((uintptr_t)it.blocks[b] & 15u) return PYRIT_EALIGN;
+  }
   const int nout = (int)outs.size();
   for (int r0 = 0; r0 < nout; r0 += kMaxOut) {
     HostPass hp;
     hp.k = (uint32_t)pl->k;
     hp.S = (uint32_t)it.slice_bytes;
+    hp.pitch = (uint32_t)pitch;
+    hp.w = (uint32_t)pl->w;
     hp.ring = pl->ring;
     hp.nout = (uint32_t)std::min(kMaxOut, nout - r0);
     for (int b : ins) hp.in.push_back((uint64_t)(uintptr_t)it.blocks[b]);
@@ -195,6 +298,11 @@ int item_passes(const pyrit_batch_item &it, std::vector<HostPass> *out, uint64_t
   return PYRIT_OK;
 }
 
+// Bytes an item moves, plus a fixed per-item charge for its start-up.
+uint64_t item_cost(const HostPass &hp, const WorkItem &wi) {
+  return (uint64_t)(hp.k + hp.nout) * hp.w * (wi.col1 - wi.col0) + (uint64_t)hp.k * hp.w * 1024u;
+}
+
 }  // namespace
 
 extern "C" {
@@ -205,9 +313,9 @@ int pyrit_batch_create(const pyrit_batch_item *items, int n_items, const pyrit_t
   *out = nullptr;
   pyrit_tune t{};
   if (tune) t = *tune;
-  if (t.wg_threads == 0) t.wg_threads = 256;
-  if (!batch_kernel_fn(t.wg_threads)) return PYRIT_EINVAL;
-  if (t.tile_bytes < 0 || t.grid < 0) return PYRIT_EINVAL;
+  if (t.mode < 0 || t.mode > 2 || t.tile_bytes < 0 || t.grid < 0) return PYRIT_EINVAL;
+  if (t.wg_threads == 0) t.wg_threads = 128;
+  if (t.wg_threads != 64 && t.wg_threads != 128 && t.wg_threads != 256) return PYRIT_EINVAL;
 
   std::unique_ptr<pyrit_batch> b(new (std::nothrow) pyrit_batch());
   if (!b) return PYRIT_ENOMEM;
@@ -216,43 +324,105 @@ int pyrit_batch_create(const pyrit_batch_item *items, int n_items, const pyrit_t
     int rc = item_passes(items[i], &passes, &b->moved);
     if (rc) return rc;
   }
+  const uint32_t wpw = (uint32_t)t.wg_threads / 64;
+  const bool persistent = t.mode != kModeGrid;
+  b->fn = persistent ? persistent_fn(t.wg_threads, t.mode) : grid_fn(t.wg_threads);
 
-  // Resident grid: as many workgroups as fit on every CU at once.
-  int dev = 0, ncu = 0, per_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return PYRIT_EHIP;
-  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    return PYRIT_EHIP;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel_fn(t.wg_threads),
-                                                   t.wg_threads, 0) != hipSuccess)
-    return PYRIT_EHIP;
-  const int grid = t.grid ? t.grid : std::max(1, per_cu * ncu);
-  const uint32_t total_waves = (uint32_t)grid * (uint32_t)(t.wg_threads / 64);
+  int grid = 0;
+  uint32_t total_waves = 0;
+  if (persistent) {
+    int dev = 0, ncu = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return PYRIT_EHIP;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return PYRIT_EHIP;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, b->fn, t.wg_threads, 0) != hipSuccess)
+      return PYRIT_EHIP;
+    grid = t.grid ? t.grid : std::max(1, per_cu * ncu);
+    // every sub-queue needs at least one workgroup to drain it
+    if (t.mode == kModeQueue) grid = std::max(grid, kGroups);
+    total_waves = (uint32_t)grid * wpw;
+  }
 
-  // Tile width: enough items for every wave to take several, at least one
-  // wave-wide chunk, at most 64 KiB of columns.
+  // Work items.  grid mode: one item per workgroup, one chunk per wave, the
+  // passes in ring order so each ring's workgroups are dispatched together.
+  // persistent modes: tiles of several chunks, enough for every wave to take
+  // a few, at most 64 KiB of columns.
+  if (!persistent)
+    std::stable_sort(passes.begin(), passes.end(),
+                     [](const HostPass &x, const HostPass &y) { return x.ring < y.ring; });
   uint64_t cols = 0;
   for (auto &hp : passes) cols += hp.S;
   std::vector<WorkItem> work;
   for (size_t pi = 0; pi < passes.size(); ++pi) {
     const HostPass &hp = passes[pi];
-    const uint32_t chunk = 64u * 4u * kBatchV[hp.ring];
-    uint64_t T = t.tile_bytes ? (uint64_t)t.tile_bytes : cols / ((uint64_t)total_waves * 4 + 1);
-    T = std::max<uint64_t>(chunk, std::min<uint64_t>(T, 65536));
-    T = align_up(T, chunk);
+    const uint32_t chunk = chunk_bytes(hp.ring);
+    uint64_t T;
+    if (!persistent) {
+      T = (uint64_t)chunk * wpw;
+    } else {
+      T = t.tile_bytes ? (uint64_t)t.tile_bytes : cols / ((uint64_t)total_waves * 4 + 1);
+      T = align_up(std::max<uint64_t>(chunk, std::min<uint64_t>(T, 65536)), chunk);
+    }
     const uint32_t end = (uint32_t)align_up(hp.S, chunk);
     for (uint64_t c = 0; c < end; c += T)
       work.push_back({(uint32_t)pi, (uint32_t)c, (uint32_t)std::min<uint64_t>(c + T, end),
                       (uint32_t)hp.ring});
   }
-  // Ring-major order keeps one ring's code hot in each CU's instruction cache;
-  // within a ring, tiles stay in stripe order.
+  // Ring-major order keeps one ring's code hot in each CU's instruction
+  // cache; within a ring, tiles stay in stripe order.
   std::stable_sort(work.begin(), work.end(),
                    [](const WorkItem &x, const WorkItem &y) { return x.ring < y.ring; });
 
-  // Device image: counters | passes | items | pointer and lift tables.
-  const size_t off_pass = 256;
+  std::vector<uint32_t> starts;
+  if (t.mode == kModeQueue) {
+    // sub-queue g takes items g, g + kGroups, ... (each stays ring-major)
+    std::vector<WorkItem> reord;
+    reord.reserve(work.size());
+    starts.push_back(0);
+    for (int g = 0; g < kGroups; ++g) {
+      for (size_t i = g; i < work.size(); i += kGroups) reord.push_back(work[i]);
+      starts.push_back((uint32_t)reord.size());
+    }
+    work.swap(reord);
+  } else if (t.mode == kModeStatic) {
+    // longest item first onto the least-loaded wave
+    std::vector<uint32_t> order(work.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (uint32_t)i;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
+      return item_cost(passes[work[x].pass], work[x]) > item_cost(passes[work[y].pass], work[y]);
+    });
+    typedef std::pair<uint64_t, uint32_t> LW;
+    std::priority_queue<LW, std::vector<LW>, std::greater<LW>> heap;
+    for (uint32_t w = 0; w < total_waves; ++w) heap.push({0, w});
+    std::vector<std::vector<uint32_t>> lists(total_waves);
+    for (uint32_t i : order) {
+      LW top = heap.top();
+      heap.pop();
+      lists[top.second].push_back(i);
+      heap.push({top.first + item_cost(passes[work[i].pass], work[i]), top.second});
+    }
+    std::vector<WorkItem> reord;
+    reord.reserve(work.size());
+    starts.push_back(0);
+    for (auto &ls : lists) {
+      std::sort(ls.begin(), ls.end());  // ring-major, stripe order within a wave
+      for (uint32_t i : ls) reord.push_back(work[i]);
+      starts.push_back((uint32_t)reord.size());
+    }
+    work.swap(reord);
+  }
+  if (!persistent) {
+    grid = (int)work.size();
+    // start index of each pass's items (items are in pass order)
+    starts.assign(passes.size() + 1, (uint32_t)work.size());
+    for (size_t i = work.size(); i-- > 0;) starts[work[i].pass] = (uint32_t)i;
+  }
+
+  // Device image: counters | starts | passes | items | pointer and lift tables.
+  const size_t off_start = (size_t)kGroups * 64;
+  const size_t off_pass = align_up(off_start + starts.size() * 4, 256);
   const size_t off_item = align_up(off_pass + passes.size() * sizeof(PassDesc), 256);
-  size_t off_tab = align_up(off_item + work.size() * sizeof(WorkItem), 256);
+  const size_t off_tab = align_up(off_item + work.size() * sizeof(WorkItem), 256);
   size_t tab_bytes = 0;
   for (auto &hp : passes)
     tab_bytes += align_up(hp.in.size() * 8, 16) + align_up(hp.out.size() * 8, 16) + hp.lift.size() * 4;
@@ -267,6 +437,7 @@ int pyrit_batch_create(const pyrit_batch_item *items, int n_items, const pyrit_t
     d.k = hp.k;
     d.nout = hp.nout;
     d.S = hp.S;
+    d.pitch = hp.pitch;
     d.ring = (uint32_t)hp.ring;
     d.in_tab = base + cur;
     std::memcpy(&img[cur], hp.in.data(), hp.in.size() * 8);
@@ -279,23 +450,30 @@ int pyrit_batch_create(const pyrit_batch_item *items, int n_items, const pyrit_t
     cur += hp.lift.size() * 4;
     std::memcpy(&img[off_pass + pi * sizeof(PassDesc)], &d, sizeof(d));
   }
+  if (!starts.empty()) std::memcpy(&img[off_start], starts.data(), starts.size() * 4);
   if (!work.empty()) std::memcpy(&img[off_item], work.data(), work.size() * sizeof(WorkItem));
   if (hipMemcpy(b->dmem, img.data(), total, hipMemcpyHostToDevice) != hipSuccess) return PYRIT_EHIP;
 
-  b->args.counters = (uint32_t *)b->dmem;
+  b->args.counters = (uint64_t *)b->dmem;
+  b->args.starts = (const uint32_t *)((uint8_t *)b->dmem + off_start);
   b->args.passes = (const PassDesc *)((uint8_t *)b->dmem + off_pass);
   b->args.items = (const WorkItem *)((uint8_t *)b->dmem + off_item);
   b->args.n_items = (uint32_t)work.size();
   b->args.total_waves = total_waves;
-  b->args.dynamic = t.static_queue ? 0u : 1u;
+  b->args.n_passes = (uint32_t)passes.size();
+  b->mode = t.mode;
   b->grid = grid;
   b->wg = t.wg_threads;
   b->n_passes = (int)passes.size();
 
+  if (work.empty()) {
+    *out = b.release();
+    return PYRIT_OK;
+  }
   if (hipGraphCreate(&b->graph, 0) != hipSuccess) return PYRIT_EHIP;
   hipKernelNodeParams kp{};
   void *kargs[] = {&b->args};
-  kp.func = const_cast<void *>(batch_kernel_fn(b->wg));
+  kp.func = const_cast<void *>(b->fn);
   kp.gridDim = dim3(b->grid);
   kp.blockDim = dim3(b->wg);
   kp.sharedMemBytes = 0;
@@ -318,7 +496,7 @@ int pyrit_batch_launch_direct(pyrit_batch *batch, void *stream) {
   if (!batch) return PYRIT_EINVAL;
   if (batch->args.n_items == 0) return PYRIT_OK;
   void *kargs[] = {&batch->args};
-  return hipLaunchKernel(batch_kernel_fn(batch->wg), dim3(batch->grid), dim3(batch->wg), kargs, 0,
+  return hipLaunchKernel(batch->fn, dim3(batch->grid), dim3(batch->wg), kargs, 0,
                          (hipStream_t)stream) == hipSuccess
              ? PYRIT_OK
              : PYRIT_EHIP;

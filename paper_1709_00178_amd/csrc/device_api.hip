@@ -37,11 +37,12 @@ static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 // Run the passes for `nout` outputs of a lifted k-column matrix L (row r of
 // L belongs to out[r]), at most kMaxOut outputs per pass.
 static int run_passes(const pyrit_plan *pl, const uint8_t *const *in, uint8_t *const *out, int nout,
-                      const uint32_t *L, size_t S, int vec_bytes, void *stream) {
+                      const uint32_t *L, size_t S, size_t pitch, int vec_bytes, void *stream) {
   PassArgs a;
   std::memset(&a, 0, sizeof(a));
   a.k = (uint32_t)pl->k;
   a.S = (uint32_t)S;
+  a.pitch = (uint32_t)pitch;
   for (int j = 0; j < pl->k; ++j) {
     if (!in[j]) return PYRIT_EINVAL;
     if (!aligned16(in[j])) return PYRIT_EALIGN;
@@ -70,26 +71,27 @@ using namespace pyrit;
 
 extern "C" {
 
-int pyrit_encode_vec(const pyrit_plan *plan, const uint8_t *const *data, uint8_t *const *parity,
-                     size_t slice_bytes, int vec_bytes, void *stream) {
+int pyrit_encode_ex(const pyrit_plan *plan, const uint8_t *const *data, uint8_t *const *parity,
+                    size_t slice_bytes, size_t slice_pitch, int vec_bytes, void *stream) {
   if (!plan || !data || !parity) return PYRIT_EINVAL;
   if (plan->ring < 0) return PYRIT_EUNSUPPORTED;
   if (vec_bytes != 0 && vec_bytes != 4 && vec_bytes != 8 && vec_bytes != 16) return PYRIT_EINVAL;
-  int rc = check_slices(plan->w, slice_bytes);
+  int rc = check_slices(plan->w, slice_bytes, &slice_pitch);
   if (rc) return rc;
-  return run_passes(plan, data, parity, plan->m, plan->L.data(), slice_bytes, vec_bytes, stream);
+  return run_passes(plan, data, parity, plan->m, plan->L.data(), slice_bytes, slice_pitch,
+                    vec_bytes, stream);
 }
 
 int pyrit_encode(const pyrit_plan *plan, const uint8_t *const *data, uint8_t *const *parity,
                  size_t slice_bytes, void *stream) {
-  return pyrit_encode_vec(plan, data, parity, slice_bytes, 0, stream);
+  return pyrit_encode_ex(plan, data, parity, slice_bytes, 0, 0, stream);
 }
 
-int pyrit_decode(const pyrit_plan *plan, const int *erased, int n_erased, uint8_t *const *blocks,
-                 size_t slice_bytes, void *stream) {
+int pyrit_decode_ex(const pyrit_plan *plan, const int *erased, int n_erased, uint8_t *const *blocks,
+                    size_t slice_bytes, size_t slice_pitch, void *stream) {
   if (!plan || !blocks) return PYRIT_EINVAL;
   if (plan->ring < 0) return PYRIT_EUNSUPPORTED;
-  int rc = check_slices(plan->w, slice_bytes);
+  int rc = check_slices(plan->w, slice_bytes, &slice_pitch);
   if (rc) return rc;
   std::shared_ptr<const DecodeEntry> ent;
   rc = decode_entry(plan, erased, n_erased, &ent);
@@ -99,7 +101,13 @@ int pyrit_decode(const pyrit_plan *plan, const int *erased, int n_erased, uint8_
   uint8_t *out[PYRIT_MMAX];
   for (int j = 0; j < plan->k; ++j) in[j] = blocks[ent->surv[j]];
   for (size_t e = 0; e < ent->outs.size(); ++e) out[e] = blocks[ent->outs[e]];
-  return run_passes(plan, in, out, (int)ent->outs.size(), ent->L.data(), slice_bytes, 0, stream);
+  return run_passes(plan, in, out, (int)ent->outs.size(), ent->L.data(), slice_bytes, slice_pitch,
+                    0, stream);
+}
+
+int pyrit_decode(const pyrit_plan *plan, const int *erased, int n_erased, uint8_t *const *blocks,
+                 size_t slice_bytes, void *stream) {
+  return pyrit_decode_ex(plan, erased, n_erased, blocks, slice_bytes, 0, stream);
 }
 
 }  // extern "C"

@@ -38,7 +38,8 @@ struct PassArgs {
   uint8_t *out[kMaxOut];
   uint32_t lift[PYRIT_KMAX][kMaxOut];
   uint32_t k;
-  uint32_t S;
+  uint32_t S;      // column bytes per slice
+  uint32_t pitch;  // bytes from one slice to the next (>= S)
 };
 
 // Lanes' column width in bytes used when the caller does not choose.
@@ -76,5 +77,6 @@ namespace pyrit {
 // Decoding matrix for a pattern (cached on the plan).
 int decode_entry(const pyrit_plan *plan, const int *erased, int n_erased,
                  std::shared_ptr<const DecodeEntry> *out);
-int check_slices(int w, size_t S);
+// Validates slice size S and slice pitch (0 is replaced by S).
+int check_slices(int w, size_t S, size_t *pitch);
 }  // namespace pyrit

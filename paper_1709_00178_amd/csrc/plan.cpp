@@ -17,9 +17,12 @@ int ring_id(int w, int n, uint32_t p) {
   return -1;
 }
 
-int check_slices(int w, size_t S) {
-  if (S == 0 || S % 64 != 0) return PYRIT_EALIGN;
-  if ((uint64_t)S * (uint64_t)w >= (uint64_t)PYRIT_SMAX_TOTAL) return PYRIT_EINVAL;
+int check_slices(int w, size_t S, size_t *pitch) {
+  if (*pitch == 0) *pitch = S;
+  if (S == 0 || S % 64 != 0 || *pitch % 64 != 0) return PYRIT_EALIGN;
+  if (*pitch < S) return PYRIT_EINVAL;
+  if ((uint64_t)(w - 1) * (uint64_t)*pitch + (uint64_t)S >= (uint64_t)PYRIT_SMAX_TOTAL)
+    return PYRIT_EINVAL;
   return PYRIT_OK;
 }
 

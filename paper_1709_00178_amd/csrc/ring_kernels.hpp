@@ -108,20 +108,23 @@ __device__ __forceinline__ void reduce_mod_p(T (&acc)[N]) {
 // memory traffic (used for prefetches past the last block).
 template <int W, int V>
 __device__ __forceinline__ void load_block(typename Vec<V>::T (&d)[W], const uint8_t *base,
-                                           uint32_t bytes, uint32_t S, uint32_t col) {
+                                           uint32_t bytes, uint32_t pitch, uint32_t col) {
   const __amdgpu_buffer_rsrc_t r = block_rsrc(base, bytes);
 #pragma unroll
-  for (int t = 0; t < W; ++t) d[t] = bload<V>(r, col, t * S);
+  for (int t = 0; t < W; ++t) d[t] = bload<V>(r, col, t * pitch);
 }
 
 // One lane column of one pass.  Src supplies wave-uniform values:
-//   k(), S(), nout(), in(j), out(r), lift(j, r).  Rows r >= nout() must have
+//   k(), S(), pitch(), nout(), in(j), out(r), lift(j, r); slice t of a block
+//   starts t * pitch() bytes after its base.  Rows r >= nout() must have
 //   zero lifted coefficients; they are neither reduced nor stored.
 template <int W, int N, uint32_t P, int MO, int V, class Src>
 __device__ __forceinline__ void code_column(const Src &src, uint32_t col, bool live) {
   typedef typename Vec<V>::T T;
   const int k = src.k();
   const uint32_t S = src.S();
+  const uint32_t pitch = src.pitch();    // slice stride (>= S)
+  const uint32_t span = (W - 1) * pitch + S;  // bytes of a block holding slices
   T acc[MO][N];
 #pragma unroll
   for (int r = 0; r < MO; ++r)
@@ -134,7 +137,7 @@ __device__ __forceinline__ void code_column(const Src &src, uint32_t col, bool l
   T d[2][W];
   auto prefetch = [&](int slot, int jj) {
     const bool ok = jj < k;
-    load_block<W, V>(d[slot], src.in(ok ? jj : k - 1), ok ? W * S : 0u, S, col);
+    load_block<W, V>(d[slot], src.in(ok ? jj : k - 1), ok ? span : 0u, pitch, col);
   };
   prefetch(0, 0);
   for (int j = 0; j < k; j += 2) {
@@ -152,9 +155,72 @@ __device__ __forceinline__ void code_column(const Src &src, uint32_t col, bool l
   for (int r = 0; r < MO; ++r) {
     if (r >= src.nout()) break;
     reduce_mod_p<W, N, P, T>(acc[r]);
-    const __amdgpu_buffer_rsrc_t o = block_rsrc(src.out(r), W * S);
+    const __amdgpu_buffer_rsrc_t o = block_rsrc(src.out(r), span);
 #pragma unroll
-    for (int t = 0; t < W; ++t) bstore<V>(acc[r][t], o, col, t * S);
+    for (int t = 0; t < W; ++t) bstore<V>(acc[r][t], o, col, t * pitch);
+  }
+}
+
+// A run of consecutive chunks [col0, col1) of one pass, coded by one wave
+// (chunk = 64 lanes x 4V bytes).  The block loads form one continuous
+// stream: while chunk c's last block is accumulated, chunk c+1's first block
+// is already in flight, so the wave never drains its load pipeline between
+// chunks.
+template <int W, int N, uint32_t P, int MO, int V, class Src>
+__device__ __forceinline__ void code_tile(const Src &src, uint32_t col0, uint32_t col1,
+                                          uint32_t lane) {
+  typedef typename Vec<V>::T T;
+  constexpr uint32_t kChunk = 64u * 4u * V;
+  const int k = src.k();
+  const uint32_t S = src.S();
+  const uint32_t pitch = src.pitch();    // slice stride (>= S)
+  const uint32_t span = (W - 1) * pitch + S;  // bytes of a block holding slices
+  T acc[MO][N];
+#pragma unroll
+  for (int r = 0; r < MO; ++r)
+#pragma unroll
+    for (int i = 0; i < N; ++i) acc[r][i] = (T)0;
+
+  T d[2][W];
+  // prefetch of (chunk base cb, block jj); cb >= col1 means past the end
+  auto prefetch = [&](int slot, uint32_t cb, int jj) {
+    const bool ok = cb < col1;
+    load_block<W, V>(d[slot], src.in(ok ? jj : 0), ok ? span : 0u, pitch, cb + lane * 4u * V);
+  };
+  uint32_t cb = col0;  // chunk being accumulated
+  int j = 0;           // block being accumulated
+  prefetch(0, cb, 0);
+  while (cb < col1) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      // next step: block j+1 of this chunk, or block 0 of the next chunk
+      const bool last = j + 1 == k;
+      prefetch(q ^ 1, last ? cb + kChunk : cb, last ? 0 : j + 1);
+#pragma unroll
+      for (int r = 0; r < MO; ++r) rot_acc<W, N, 0, T>(acc[r], d[q], src.lift(j, r));
+      if (last) {
+        const uint32_t col = cb + lane * 4u * V;
+        if (col < S) {
+#pragma unroll
+          for (int r = 0; r < MO; ++r) {
+            if (r >= src.nout()) break;
+            reduce_mod_p<W, N, P, T>(acc[r]);
+            const __amdgpu_buffer_rsrc_t o = block_rsrc(src.out(r), span);
+#pragma unroll
+            for (int t = 0; t < W; ++t) bstore<V>(acc[r][t], o, col, t * pitch);
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < MO; ++r)
+#pragma unroll
+          for (int i = 0; i < N; ++i) acc[r][i] = (T)0;
+        cb += kChunk;
+        j = 0;
+        if (cb >= col1) break;
+      } else {
+        ++j;
+      }
+    }
   }
 }
 
@@ -163,6 +229,7 @@ struct KernargSrc {
   const PassArgs &a;
   __device__ int k() const { return (int)a.k; }
   __device__ uint32_t S() const { return a.S; }
+  __device__ uint32_t pitch() const { return a.pitch; }
   __device__ int nout() const { return kMaxOut; }
   __device__ const uint8_t *in(int j) const { return a.in[j]; }
   __device__ uint8_t *out(int r) const { return a.out[r]; }

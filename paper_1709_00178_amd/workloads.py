@@ -112,14 +112,36 @@ class Stripe:
     erased: tuple = ()          # empty: encode; else: decode of these blocks
     stripe: int = 0             # index used in block keys
     seed: int = BASE_SEED
+    pad: int = 0                # bytes between consecutive slices in memory
 
     @property
     def S(self) -> int:
         return slice_bytes(self.B, self.w)
 
     @property
-    def block_len(self) -> int:
+    def pitch(self) -> int:
+        """Slice stride in memory: S for the packed layout, S + pad else."""
+        return self.S + self.pad
+
+    @property
+    def data_len(self) -> int:
+        """Bytes of the w slices (the logical block)."""
         return self.w * self.S
+
+    @property
+    def block_len(self) -> int:
+        """Bytes a block occupies in memory: w slices at the pitch."""
+        return self.w * self.pitch
+
+    @property
+    def nrandom(self) -> int:
+        """Memory bytes of a block holding generator output (zero beyond).
+        Packed blocks carry B random bytes; padded blocks (which require
+        B == w * S) are random over their whole memory, padding included."""
+        if self.pad == 0:
+            return self.B
+        assert self.B == self.w * self.S, "padded layouts need B == w * S"
+        return self.block_len
 
     def key(self, block: int) -> int:
         return block_key(self.seed, self.stripe, block)
@@ -127,7 +149,7 @@ class Stripe:
     def moved_bytes(self) -> int:
         """Bytes a coding pass reads and writes: (k + outputs) * w * S."""
         outs = len(self.erased) if self.erased else self.m
-        return (self.k + outs) * self.block_len
+        return (self.k + outs) * self.data_len
 
 
 # ---------------------------------------------------------------- workloads
@@ -238,4 +260,11 @@ def host_blocks(st: Stripe, blocks=None) -> list:
     valid input; codeword round trips are checked separately.
     """
     ids = survivors(st) if blocks is None else blocks
-    return [block_bytes(st.key(j), st.block_len, st.B) for j in ids]
+    return [logical(st, block_bytes(st.key(j), st.block_len, st.nrandom)) for j in ids]
+
+
+def logical(st: Stripe, mem: np.ndarray) -> np.ndarray:
+    """The w slices of a block's memory image, packed (w * S bytes)."""
+    if st.pad == 0:
+        return mem
+    return np.concatenate([mem[t * st.pitch:t * st.pitch + st.S] for t in range(st.w)])

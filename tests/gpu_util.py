@@ -20,7 +20,7 @@ def dev_empty(nbytes):
 def dev_block(st, block_id):
     """A device block holding the generator's bytes for block `block_id`."""
     t = dev_empty(st.block_len)
-    P.fill_random(t, st.key(block_id), nrandom=st.B)
+    P.fill_random(t, st.key(block_id), nrandom=st.nrandom)
     return t
 
 
@@ -28,15 +28,17 @@ def to_host(t):
     return t.cpu().numpy()
 
 
-def gather_cols(buf, S, w, cols):
-    """Mini block made of the given columns of every slice (w x len(cols))."""
-    return np.ascontiguousarray(np.stack([buf[t * S + cols] for t in range(w)]).reshape(-1))
+def gather_cols(buf, S, w, cols, pitch=None):
+    """Mini block made of the given columns of every slice (w x len(cols));
+    slice t starts at t * pitch (pitch defaults to S)."""
+    pitch = S if pitch is None else pitch
+    return np.ascontiguousarray(np.stack([buf[t * pitch + cols] for t in range(w)]).reshape(-1))
 
 
 def gen_cols(st, block_id, cols):
     """Generator bytes of a block at the given columns of every slice."""
-    offs = (np.arange(st.w)[:, None] * st.S + cols[None, :]).reshape(-1)
-    return W.block_bytes_at(st.key(block_id), offs, st.B)
+    offs = (np.arange(st.w)[:, None] * st.pitch + cols[None, :]).reshape(-1)
+    return W.block_bytes_at(st.key(block_id), offs, st.nrandom)
 
 
 def sample_cols(S, n, seed):
@@ -76,7 +78,7 @@ def stripe_buffers(st, arena, fill=True):
     for b in ins:
         blocks[b] = arena.take(st.block_len)
         if fill:
-            P.fill_random(blocks[b], st.key(b), nrandom=st.B)
+            P.fill_random(blocks[b], st.key(b), nrandom=st.nrandom)
     for b in outs:
         blocks[b] = arena.take(st.block_len)
     return blocks, ins, outs

@@ -75,39 +75,42 @@ def test_batch_single_stripe_every_shape():
     host = W.host_blocks(st)
     want = oracle.Field(st.w, st.p).encode(plans.get(st).G, host, st.S, nthreads=4)
     for wg in [64, 128, 256]:
-        for static in [False, True]:
-            for tile in [0, 512, 4096]:
-                b = P.Batch(items, tile_bytes=tile, wg_threads=wg, static_queue=static)
-                for launch in [b.launch, b.launch_direct]:
+        for mode in ["grid", "queue", "static"]:
+            for tile in ([0] if mode == "grid" else [0, 512, 4096]):
+                b = P.Batch(items, mode=mode, tile_bytes=tile, wg_threads=wg)
+                for launch in [b.launch, b.launch_direct, b.launch]:
                     _clear_outputs(bufs, 0xEE)
                     launch()
                     sync()
                     for i in range(st.m):
                         got = to_host(bufs[0][0][st.k + i])
-                        assert np.array_equal(got, want[i]), (wg, static, tile, i)
+                        assert np.array_equal(got, want[i]), (wg, mode, tile, i)
                 b.close()
 
 
-def test_batch_graph_replays_with_eager_work_between():
-    """Each replay recomputes every output; eager fills between replays."""
+@pytest.mark.parametrize("mode", ["grid", "queue", "static"])
+def test_batch_graph_replays_with_eager_work_between(mode):
+    """Each replay recomputes every output; eager fills between replays (the
+    queue mode's claim counters carry over from launch to launch)."""
     stripes = W.c2(8)
     plans = PlanCache()
     arena = Arena(sum(stripe_bytes_needed(s) for s in stripes) + 4096)
     bufs, items = _build(stripes, plans, arena)
-    b = P.Batch(items)
-    for rep in range(4):
+    b = P.Batch(items, mode=mode, tile_bytes=4096 if mode != "grid" else 0)
+    for rep in range(5):
         _clear_outputs(bufs, rep * 17)
         b.launch()
         sync()
         _check_stripes(stripes, bufs, plans, ncols=8, seed=rep)
 
 
-def test_c2_all_stripes_one_launch():
+@pytest.mark.parametrize("mode", ["grid", "queue", "static"])
+def test_c2_all_stripes_one_launch(mode):
     stripes = W.c2()
     plans = PlanCache()
     arena = Arena(sum(stripe_bytes_needed(s) for s in stripes) + 4096)
     bufs, items = _build(stripes, plans, arena)
-    b = P.Batch(items)
+    b = P.Batch(items, mode=mode)
     info = b.info()
     assert info["passes"] == 256
     assert info["moved_bytes"] == sum(s.moved_bytes() for s in stripes)
@@ -116,14 +119,15 @@ def test_c2_all_stripes_one_launch():
     _check_stripes(stripes, bufs, plans, ncols=12)
 
 
-def test_c3_all_4096_uneven_stripes_one_launch():
+@pytest.mark.parametrize("mode", ["grid", "queue", "static"])
+def test_c3_all_4096_uneven_stripes_one_launch(mode):
     """The uneven batch: w in {4,8,10}, k in [4,16], m in [2,4], 4 KiB..4 MiB
-    blocks, 30% decodes, all in one persistent launch."""
+    blocks, 30% decodes, all in one launch."""
     stripes = W.c3()
     plans = PlanCache()
     arena = Arena(sum(stripe_bytes_needed(s) for s in stripes) + 4096)
     bufs, items = _build(stripes, plans, arena)
-    b = P.Batch(items)
+    b = P.Batch(items, mode=mode)
     info = b.info()
     assert info["moved_bytes"] == sum(s.moved_bytes() for s in stripes)
     _clear_outputs(bufs, 0x77)
@@ -145,11 +149,14 @@ def test_batch_matches_plain_kernel_bytes():
     par_plain = [arena.take(st.block_len) for _ in range(st.m)]
     par_batch = [arena.take(st.block_len) for _ in range(st.m)]
     plan.encode(data, par_plain, st.S)
-    b = P.Batch([(plan, [], data + par_batch, st.S)])
-    b.launch()
-    sync()
-    for a, c in zip(par_plain, par_batch):
-        assert torch.equal(a, c)
+    for mode in ["grid", "queue", "static"]:
+        for t in par_batch:
+            t.zero_()
+        b = P.Batch([(plan, [], data + par_batch, st.S)], mode=mode)
+        b.launch()
+        sync()
+        for a, c in zip(par_plain, par_batch):
+            assert torch.equal(a, c), mode
     # decode two data blocks and two parity blocks through the batch path
     er = [1, 7, 11, 14]
     blocks = data + par_plain
@@ -180,6 +187,8 @@ def test_batch_errors():
     with pytest.raises(P.PyritError) as e:
         P.Batch([(plan, [], blocks, st.S)], wg_threads=96)
     assert e.value.code == -1
+    with pytest.raises(ValueError):
+        P.Batch([(plan, [], blocks, st.S)], mode="fifo")
     empty = P.Batch([])
     empty.launch()
     sync()

@@ -285,3 +285,48 @@ def test_error_paths():
         plan.encode([a, bufs[0]], bufs[1:], st.S, vec_bytes=12)
     assert e.value.code == -1
     sync()
+
+
+@pytest.mark.parametrize("w,n,p,pad", [(8, 17, 0x139, 4096), (10, 11, 0x7FF, 320), (4, 5, 0x1F, 64)])
+def test_slice_pitch_plain_and_batched(w, n, p, pad):
+    """Blocks whose slices sit `pad` bytes apart: the padding is never read or
+    written, and the coded bytes equal the oracle on the packed slices."""
+    torch = torch_mod()
+    k, m = 6, 3
+    st = W.Stripe(w, n, p, k=k, m=m, B=w * 64 * 300, seed=31, pad=pad)
+    plan = P.Plan(w, n, p, k, m)
+    data = [dev_block(st, j) for j in range(k)]
+    host = W.host_blocks(st)
+    want = oracle.Field(w, p).encode(plan.G, host, st.S, nthreads=4)
+    for path in ["plain", "grid", "queue"]:
+        par = [dev_empty(st.block_len) for _ in range(m)]
+        for t in par:
+            t.fill_(0xB7)
+        if path == "plain":
+            plan.encode(data, par, st.S, pitch=st.pitch)
+        else:
+            P.Batch([(plan, [], data + par, st.S, st.pitch)], mode=path).launch()
+        sync()
+        for i in range(m):
+            mem = to_host(par[i])
+            assert np.array_equal(W.logical(st, mem), want[i]), (path, i)
+            for t in range(w):
+                gap = mem[t * st.pitch + st.S:(t + 1) * st.pitch]
+                assert (gap == 0xB7).all(), (path, i, t)
+    # decode through the pitch-aware path
+    code = data + [dev_empty(st.block_len) for _ in range(m)]
+    plan.encode(data, code[k:], st.S, pitch=st.pitch)
+    er = [0, 4, 7]
+    saved = [code[e].clone() for e in er]
+    for e in er:
+        code[e].fill_(0)
+    plan.decode(er, code, st.S, pitch=st.pitch)
+    sync()
+    for e, s_ in zip(er, saved):
+        a, b = W.logical(st, to_host(code[e])), W.logical(st, to_host(s_))
+        assert np.array_equal(a, b), e
+    with pytest.raises(P.PyritError):
+        plan.encode(data, code[k:], st.S, pitch=st.S - 64)
+    with pytest.raises(P.PyritError):
+        plan.encode(data, code[k:], st.S, pitch=st.S + 32)
+    del torch
