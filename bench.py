@@ -334,13 +334,45 @@ def bench_c3(args, stream, out, log):
     torch.cuda.empty_cache()
 
 
+def bench_c4(args, stream, out, log):
+    """Served mix: Poisson arrivals at 20k/s for 2 s of requests from the
+    uneven distribution plus 5% k=10 m=4 GF(2^8) requests of 64 MiB blocks;
+    64 GiB output pool; continuous batching against one request per launch."""
+    import torch
+
+    from paper_1709_00178_amd import serve
+    from paper_1709_00178_amd import workloads as W
+    inputs = serve.InputPool(16 << 30, key=W.BASE_SEED + 4)
+    plans = {}
+    for key, rate, dur in [("c4", 20000.0, 2.0), ("c4_stress_80k", 80000.0, 1.0)]:
+        trace = W.c4(rate=rate, duration_s=dur)
+        t0 = time.perf_counter()
+        prep = serve.prepare(trace, inputs, plans)
+        prep_s = time.perf_counter() - t0
+        offered = sum(r.stripe.k * r.stripe.B for r in trace) / dur
+        res = {"rate_per_s": rate, "duration_s": dur, "requests": len(trace),
+               "offered_GBps_data": round(offered / 1e9, 1), "prepare_s": round(prep_s, 2),
+               "pool_GiB": 64, "slots": 4}
+        for name, per_req in [("batched", False), ("per_request_plain", True)]:
+            sv = serve.Server(pool_bytes=64 << 30, slots=4, per_request=per_req,
+                              release_outputs=True, block_skew=BLOCK_SKEW)
+            r, st = sv.run(prep.array)
+            res[name] = serve.summarize(prep, r, st)
+            log(f"{key} {name}: {res[name]}")
+            sv.close()
+            torch.cuda.empty_cache()
+        out[key] = res
+    del inputs
+    torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", default="c1,c2,c3", help="comma list of c1,c2,c3")
+    ap.add_argument("--only", default="c1,c2,c3,c4", help="comma list of c1,c2,c3,c4")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported. Stripes (or "
@@ -377,6 +409,8 @@ def main():
         bench_c2(args, stream, out, log)
     if "c3" in only:
         bench_c3(args, stream, out, log)
+    if "c4" in only:
+        bench_c4(args, stream, out, log)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

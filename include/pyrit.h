@@ -241,6 +241,79 @@ int pyrit_batch_info(const pyrit_batch *batch, int *n_passes, int *n_work_items,
 /* Release the batch.  The caller must ensure no stream still runs it. */
 void pyrit_batch_destroy(pyrit_batch *batch);
 
+/* ------------------------------------------------------------------ serving
+ * A request loop with continuous batching.  Requests arrive over time; each
+ * is admitted (FIFO) once its output blocks fit in the server's device pool,
+ * which caps the working set; whenever a launch slot (a stream) is free, all
+ * admitted requests not yet launched go to the GPU as one batch (the batch
+ * kernels above), so requests arriving while earlier ones run are coded in
+ * overlapping launches.  Plans and input buffers stay resident; the server
+ * owns the output pool, the per-slot descriptor buffers and the streams.
+ * A launch that carries a single request runs the plain kernel (arguments in
+ * the kernel-argument segment, nothing uploaded first).
+ */
+typedef struct {
+  double arrival_s;             /* seconds after the start of the run */
+  const pyrit_plan *plan;
+  int n_erased;                 /* 0: encode the m parity blocks; else decode */
+  const int *erased;            /* n_erased distinct block ids (host) */
+  const uint8_t *const *inputs; /* k device pointers: the data blocks (encode)
+                                   or the first k non-erased blocks (decode) */
+  size_t slice_bytes;
+  size_t slice_pitch;           /* 0 = slice_bytes; also the pitch of outputs */
+} pyrit_request;
+
+typedef struct {
+  double admit_s;       /* outputs allocated from the pool */
+  double launch_s;      /* its launch was enqueued */
+  double done_s;        /* the launch was seen complete */
+  uint64_t out_offset;  /* pool offset of its first output block; output r
+                           starts at out_offset + r * out_stride */
+  uint64_t out_stride;
+  int launch;           /* index of the launch that carried it */
+} pyrit_request_result;
+
+typedef struct {
+  size_t pool_bytes;     /* output pool = working-set cap (bytes) */
+  int slots;             /* launches in flight at once (1..16) */
+  int max_batch;         /* requests per launch, 0 = unlimited */
+  int per_request;       /* 1: one request per launch, plain kernel (baseline) */
+  int release_outputs;   /* 1: outputs return to the pool at completion */
+  size_t block_skew;     /* bytes left unused after each output block */
+  size_t slot_bytes;     /* descriptor buffer per slot, 0 = 64 MiB */
+  size_t large_bytes;    /* requests moving at least this many bytes launch
+                            alone, on at most slots-1 slots, so that small
+                            requests never wait behind them; 0 = off */
+  pyrit_tune tune;       /* batch executor (pyrit_batch_create's) */
+} pyrit_serve_config;
+
+typedef struct {
+  double elapsed_s;         /* first arrival to last completion */
+  int launches;
+  int max_batch_seen;
+  double mean_batch;
+  uint64_t peak_pool_bytes; /* largest pool occupancy */
+  int admission_waits;      /* requests that waited for pool space */
+  uint64_t moved_bytes;     /* (k + outputs) * w * S over all requests */
+} pyrit_serve_stats;
+
+typedef struct pyrit_server pyrit_server;
+
+/* Allocate the pool, slot streams, events and descriptor buffers. */
+int pyrit_server_create(const pyrit_serve_config *cfg, pyrit_server **out);
+
+/* Device address of the output pool (outputs are read from there). */
+void *pyrit_server_pool(const pyrit_server *server);
+
+/* Serve n requests (sorted by arrival_s) in real time from now; returns when
+ * all have completed.  res[i] receives request i's timings and output place.
+ * Returns PYRIT_EBUSY if a request can never fit (pool too small with
+ * release_outputs = 0), or the first request validation error. */
+int pyrit_server_run(pyrit_server *server, const pyrit_request *reqs, int n,
+                     pyrit_request_result *res, pyrit_serve_stats *stats);
+
+void pyrit_server_destroy(pyrit_server *server);
+
 #ifdef __cplusplus
 }
 #endif

@@ -46,6 +46,10 @@ SIGNATURES = {
     "pyrit_batch_launch_direct": (c_int, [c_vp, c_vp]),
     "pyrit_batch_info": (c_int, [c_vp, P(c_int), P(c_int), P(c_u64), P(c_int), P(c_int)]),
     "pyrit_batch_destroy": (None, [c_vp]),
+    "pyrit_server_create": (c_int, [c_vp, P(c_vp)]),
+    "pyrit_server_pool": (c_vp, [c_vp]),
+    "pyrit_server_run": (c_int, [c_vp, c_vp, c_int, c_vp, c_vp]),
+    "pyrit_server_destroy": (None, [c_vp]),
 }
 
 
@@ -80,3 +84,31 @@ def lib():
         fn.argtypes = args
     _lib = L
     return L
+
+
+class Request(ctypes.Structure):
+    """pyrit_request"""
+    _fields_ = [("arrival_s", ctypes.c_double), ("plan", c_vp), ("n_erased", c_int),
+                ("erased", P(c_int)), ("inputs", P(c_vp)), ("slice_bytes", c_size),
+                ("slice_pitch", c_size)]
+
+
+class RequestResult(ctypes.Structure):
+    """pyrit_request_result"""
+    _fields_ = [("admit_s", ctypes.c_double), ("launch_s", ctypes.c_double),
+                ("done_s", ctypes.c_double), ("out_offset", c_u64), ("out_stride", c_u64),
+                ("launch", c_int)]
+
+
+class ServeConfig(ctypes.Structure):
+    """pyrit_serve_config"""
+    _fields_ = [("pool_bytes", c_size), ("slots", c_int), ("max_batch", c_int),
+                ("per_request", c_int), ("release_outputs", c_int), ("block_skew", c_size),
+                ("slot_bytes", c_size), ("large_bytes", c_size), ("tune", Tune)]
+
+
+class ServeStats(ctypes.Structure):
+    """pyrit_serve_stats"""
+    _fields_ = [("elapsed_s", ctypes.c_double), ("launches", c_int), ("max_batch_seen", c_int),
+                ("mean_batch", ctypes.c_double), ("peak_pool_bytes", c_u64),
+                ("admission_waits", c_int), ("moved_bytes", c_u64)]

@@ -18,6 +18,7 @@ ARCH = "gfx950"
 
 SOURCES = [
     "plan.cpp",
+    "serve.cpp",
     "device_api.hip",
     "batch.hip",
     "plain_ring0.hip",
@@ -39,7 +40,8 @@ def _compile(src: str, verbose: bool) -> str:
     if src.endswith(".hip"):
         cmd = [HIPCC, "-x", "hip", *HIP_FLAGS, *COMMON, "-c", path, "-o", obj]
     else:
-        cmd = [HIPCC, "-x", "c++", *COMMON, "-c", path, "-o", obj]
+        cmd = [HIPCC, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", *COMMON,
+               "-c", path, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -219,22 +219,7 @@ static const void *persistent_fn(int wg, int mode) {
 
 using namespace pyrit;
 
-struct pyrit_batch {
-  void *dmem = nullptr;
-  BatchArgs args{};
-  const void *fn = nullptr;
-  int mode = 0;
-  int grid = 0, wg = 128;
-  int n_passes = 0;
-  uint64_t moved = 0;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  ~pyrit_batch() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    if (dmem) (void)hipFree(dmem);
-  }
-};
+// ------------------------------------------------------------ host builder
 
 namespace {
 
@@ -303,45 +288,48 @@ uint64_t item_cost(const HostPass &hp, const WorkItem &wi) {
   return (uint64_t)(hp.k + hp.nout) * hp.w * (wi.col1 - wi.col0) + (uint64_t)hp.k * hp.w * 1024u;
 }
 
+const void *kernel_fn(int mode, int wg) {
+  return mode == kModeGrid ? grid_fn(wg) : persistent_fn(wg, mode);
+}
+
 }  // namespace
 
-extern "C" {
+namespace pyrit {
 
-int pyrit_batch_create(const pyrit_batch_item *items, int n_items, const pyrit_tune *tune,
-                       pyrit_batch **out) {
-  if (!out || n_items < 0 || (n_items > 0 && !items)) return PYRIT_EINVAL;
-  *out = nullptr;
-  pyrit_tune t{};
-  if (tune) t = *tune;
-  if (t.mode < 0 || t.mode > 2 || t.tile_bytes < 0 || t.grid < 0) return PYRIT_EINVAL;
-  if (t.wg_threads == 0) t.wg_threads = 128;
-  if (t.wg_threads != 64 && t.wg_threads != 128 && t.wg_threads != 256) return PYRIT_EINVAL;
+int batch_check_tune(pyrit_tune *t) {
+  if (t->mode < 0 || t->mode > 2 || t->tile_bytes < 0 || t->grid < 0) return PYRIT_EINVAL;
+  if (t->wg_threads == 0) t->wg_threads = 128;
+  if (t->wg_threads != 64 && t->wg_threads != 128 && t->wg_threads != 256) return PYRIT_EINVAL;
+  return PYRIT_OK;
+}
 
-  std::unique_ptr<pyrit_batch> b(new (std::nothrow) pyrit_batch());
-  if (!b) return PYRIT_ENOMEM;
+int batch_resident_grid(const pyrit_tune &t, int *grid) {
+  int dev = 0, ncu = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return PYRIT_EHIP;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return PYRIT_EHIP;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel_fn(t.mode, t.wg_threads),
+                                                   t.wg_threads, 0) != hipSuccess)
+    return PYRIT_EHIP;
+  int g = t.grid ? t.grid : std::max(1, per_cu * ncu);
+  // every sub-queue needs at least one workgroup to drain it
+  if (t.mode == kModeQueue) g = std::max(g, kGroups);
+  *grid = g;
+  return PYRIT_OK;
+}
+
+int build_batch_image(const pyrit_batch_item *items, int n_items, const pyrit_tune &t,
+                      int resident_grid, uint64_t dev_base, BatchImage *bi) {
   std::vector<HostPass> passes;
+  bi->moved = 0;
   for (int i = 0; i < n_items; ++i) {
-    int rc = item_passes(items[i], &passes, &b->moved);
+    int rc = item_passes(items[i], &passes, &bi->moved);
     if (rc) return rc;
   }
   const uint32_t wpw = (uint32_t)t.wg_threads / 64;
   const bool persistent = t.mode != kModeGrid;
-  b->fn = persistent ? persistent_fn(t.wg_threads, t.mode) : grid_fn(t.wg_threads);
-
-  int grid = 0;
-  uint32_t total_waves = 0;
-  if (persistent) {
-    int dev = 0, ncu = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return PYRIT_EHIP;
-    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-      return PYRIT_EHIP;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, b->fn, t.wg_threads, 0) != hipSuccess)
-      return PYRIT_EHIP;
-    grid = t.grid ? t.grid : std::max(1, per_cu * ncu);
-    // every sub-queue needs at least one workgroup to drain it
-    if (t.mode == kModeQueue) grid = std::max(grid, kGroups);
-    total_waves = (uint32_t)grid * wpw;
-  }
+  const int grid = persistent ? resident_grid : 0;
+  const uint32_t total_waves = persistent ? (uint32_t)grid * wpw : 0u;
 
   // Work items.  grid mode: one item per workgroup, one chunk per wave, the
   // passes in ring order so each ring's workgroups are dispatched together.
@@ -410,26 +398,25 @@ int pyrit_batch_create(const pyrit_batch_item *items, int n_items, const pyrit_t
       starts.push_back((uint32_t)reord.size());
     }
     work.swap(reord);
-  }
-  if (!persistent) {
-    grid = (int)work.size();
+  } else {
     // start index of each pass's items (items are in pass order)
     starts.assign(passes.size() + 1, (uint32_t)work.size());
     for (size_t i = work.size(); i-- > 0;) starts[work[i].pass] = (uint32_t)i;
   }
 
-  // Device image: counters | starts | passes | items | pointer and lift tables.
-  const size_t off_start = (size_t)kGroups * 64;
-  const size_t off_pass = align_up(off_start + starts.size() * 4, 256);
-  const size_t off_item = align_up(off_pass + passes.size() * sizeof(PassDesc), 256);
-  const size_t off_tab = align_up(off_item + work.size() * sizeof(WorkItem), 256);
+  // Image: counters | starts | passes | items | pointer and lift tables.
+  bi->off_start = (size_t)kGroups * 64;
+  bi->off_pass = align_up(bi->off_start + starts.size() * 4, 256);
+  // grid mode derives each workgroup's item from the pass start indices, so
+  // its image carries no item records
+  const size_t n_item_recs = persistent ? work.size() : 0;
+  bi->off_item = align_up(bi->off_pass + passes.size() * sizeof(PassDesc), 256);
+  const size_t off_tab = align_up(bi->off_item + n_item_recs * sizeof(WorkItem), 256);
   size_t tab_bytes = 0;
   for (auto &hp : passes)
     tab_bytes += align_up(hp.in.size() * 8, 16) + align_up(hp.out.size() * 8, 16) + hp.lift.size() * 4;
   const size_t total = align_up(off_tab + tab_bytes, 256);
-  std::vector<uint8_t> img(total, 0);
-  if (hipMalloc(&b->dmem, total) != hipSuccess) return PYRIT_ENOMEM;
-  const uint64_t base = (uint64_t)(uintptr_t)b->dmem;
+  bi->img.assign(total, 0);
   size_t cur = off_tab;
   for (size_t pi = 0; pi < passes.size(); ++pi) {
     const HostPass &hp = passes[pi];
@@ -439,43 +426,105 @@ int pyrit_batch_create(const pyrit_batch_item *items, int n_items, const pyrit_t
     d.S = hp.S;
     d.pitch = hp.pitch;
     d.ring = (uint32_t)hp.ring;
-    d.in_tab = base + cur;
-    std::memcpy(&img[cur], hp.in.data(), hp.in.size() * 8);
+    d.in_tab = dev_base + cur;
+    std::memcpy(&bi->img[cur], hp.in.data(), hp.in.size() * 8);
     cur += align_up(hp.in.size() * 8, 16);
-    d.out_tab = base + cur;
-    std::memcpy(&img[cur], hp.out.data(), hp.out.size() * 8);
+    d.out_tab = dev_base + cur;
+    std::memcpy(&bi->img[cur], hp.out.data(), hp.out.size() * 8);
     cur += align_up(hp.out.size() * 8, 16);
-    d.lift_tab = base + cur;
-    std::memcpy(&img[cur], hp.lift.data(), hp.lift.size() * 4);
+    d.lift_tab = dev_base + cur;
+    std::memcpy(&bi->img[cur], hp.lift.data(), hp.lift.size() * 4);
     cur += hp.lift.size() * 4;
-    std::memcpy(&img[off_pass + pi * sizeof(PassDesc)], &d, sizeof(d));
+    std::memcpy(&bi->img[bi->off_pass + pi * sizeof(PassDesc)], &d, sizeof(d));
   }
-  if (!starts.empty()) std::memcpy(&img[off_start], starts.data(), starts.size() * 4);
-  if (!work.empty()) std::memcpy(&img[off_item], work.data(), work.size() * sizeof(WorkItem));
-  if (hipMemcpy(b->dmem, img.data(), total, hipMemcpyHostToDevice) != hipSuccess) return PYRIT_EHIP;
+  if (!starts.empty()) std::memcpy(&bi->img[bi->off_start], starts.data(), starts.size() * 4);
+  if (n_item_recs) std::memcpy(&bi->img[bi->off_item], work.data(), n_item_recs * sizeof(WorkItem));
+  bi->n_items = (uint32_t)work.size();
+  bi->n_passes = (uint32_t)passes.size();
+  bi->total_waves = total_waves;
+  bi->mode = t.mode;
+  bi->wg = t.wg_threads;
+  bi->grid = persistent ? grid : (int)work.size();
+  return PYRIT_OK;
+}
 
-  b->args.counters = (uint64_t *)b->dmem;
-  b->args.starts = (const uint32_t *)((uint8_t *)b->dmem + off_start);
-  b->args.passes = (const PassDesc *)((uint8_t *)b->dmem + off_pass);
-  b->args.items = (const WorkItem *)((uint8_t *)b->dmem + off_item);
-  b->args.n_items = (uint32_t)work.size();
-  b->args.total_waves = total_waves;
-  b->args.n_passes = (uint32_t)passes.size();
-  b->mode = t.mode;
-  b->grid = grid;
-  b->wg = t.wg_threads;
-  b->n_passes = (int)passes.size();
+static BatchArgs image_args(const BatchImage &bi, void *dev) {
+  BatchArgs a{};
+  a.counters = (uint64_t *)dev;
+  a.starts = (const uint32_t *)((uint8_t *)dev + bi.off_start);
+  a.passes = (const PassDesc *)((uint8_t *)dev + bi.off_pass);
+  a.items = (const WorkItem *)((uint8_t *)dev + bi.off_item);
+  a.n_items = bi.n_items;
+  a.total_waves = bi.total_waves;
+  a.n_passes = bi.n_passes;
+  return a;
+}
 
-  if (work.empty()) {
+int launch_batch_image(const BatchImage &bi, void *dev, void *stream) {
+  if (bi.n_items == 0) return PYRIT_OK;
+  BatchArgs a = image_args(bi, dev);
+  void *kargs[] = {&a};
+  return hipLaunchKernel(kernel_fn(bi.mode, bi.wg), dim3(bi.grid), dim3(bi.wg), kargs, 0,
+                         (hipStream_t)stream) == hipSuccess
+             ? PYRIT_OK
+             : PYRIT_EHIP;
+}
+
+}  // namespace pyrit
+
+struct pyrit_batch {
+  void *dmem = nullptr;
+  BatchImage bi;
+  BatchArgs args{};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~pyrit_batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (dmem) (void)hipFree(dmem);
+  }
+};
+
+extern "C" {
+
+int pyrit_batch_create(const pyrit_batch_item *items, int n_items, const pyrit_tune *tune,
+                       pyrit_batch **out) {
+  if (!out || n_items < 0 || (n_items > 0 && !items)) return PYRIT_EINVAL;
+  *out = nullptr;
+  pyrit_tune t{};
+  if (tune) t = *tune;
+  int rc = batch_check_tune(&t);
+  if (rc) return rc;
+  std::unique_ptr<pyrit_batch> b(new (std::nothrow) pyrit_batch());
+  if (!b) return PYRIT_ENOMEM;
+  // Validate the items before touching the device; the image embeds device
+  // addresses, so it is built again once the allocation exists.
+  BatchImage probe;
+  rc = build_batch_image(items, n_items, t, 1, 0, &probe);
+  if (rc) return rc;
+  int grid = 0;
+  if (t.mode != kModeGrid) {
+    rc = batch_resident_grid(t, &grid);
+    if (rc) return rc;
+    rc = build_batch_image(items, n_items, t, grid, 0, &probe);
+    if (rc) return rc;
+  }
+  if (hipMalloc(&b->dmem, probe.img.size()) != hipSuccess) return PYRIT_ENOMEM;
+  rc = build_batch_image(items, n_items, t, grid, (uint64_t)(uintptr_t)b->dmem, &b->bi);
+  if (rc) return rc;
+  if (hipMemcpy(b->dmem, b->bi.img.data(), b->bi.img.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return PYRIT_EHIP;
+  b->args = image_args(b->bi, b->dmem);
+  if (b->bi.n_items == 0) {
     *out = b.release();
     return PYRIT_OK;
   }
   if (hipGraphCreate(&b->graph, 0) != hipSuccess) return PYRIT_EHIP;
   hipKernelNodeParams kp{};
   void *kargs[] = {&b->args};
-  kp.func = const_cast<void *>(b->fn);
-  kp.gridDim = dim3(b->grid);
-  kp.blockDim = dim3(b->wg);
+  kp.func = const_cast<void *>(kernel_fn(b->bi.mode, b->bi.wg));
+  kp.gridDim = dim3(b->bi.grid);
+  kp.blockDim = dim3(b->bi.wg);
   kp.sharedMemBytes = 0;
   kp.kernelParams = kargs;
   kp.extra = nullptr;
@@ -488,28 +537,23 @@ int pyrit_batch_create(const pyrit_batch_item *items, int n_items, const pyrit_t
 
 int pyrit_batch_launch(pyrit_batch *batch, void *stream) {
   if (!batch) return PYRIT_EINVAL;
-  if (batch->args.n_items == 0) return PYRIT_OK;
+  if (batch->bi.n_items == 0) return PYRIT_OK;
   return hipGraphLaunch(batch->exec, (hipStream_t)stream) == hipSuccess ? PYRIT_OK : PYRIT_EHIP;
 }
 
 int pyrit_batch_launch_direct(pyrit_batch *batch, void *stream) {
   if (!batch) return PYRIT_EINVAL;
-  if (batch->args.n_items == 0) return PYRIT_OK;
-  void *kargs[] = {&batch->args};
-  return hipLaunchKernel(batch->fn, dim3(batch->grid), dim3(batch->wg), kargs, 0,
-                         (hipStream_t)stream) == hipSuccess
-             ? PYRIT_OK
-             : PYRIT_EHIP;
+  return launch_batch_image(batch->bi, batch->dmem, stream);
 }
 
 int pyrit_batch_info(const pyrit_batch *batch, int *n_passes, int *n_work_items,
                      uint64_t *moved_bytes, int *grid, int *wg_threads) {
   if (!batch) return PYRIT_EINVAL;
-  if (n_passes) *n_passes = batch->n_passes;
-  if (n_work_items) *n_work_items = (int)batch->args.n_items;
-  if (moved_bytes) *moved_bytes = batch->moved;
-  if (grid) *grid = batch->grid;
-  if (wg_threads) *wg_threads = batch->wg;
+  if (n_passes) *n_passes = (int)batch->bi.n_passes;
+  if (n_work_items) *n_work_items = (int)batch->bi.n_items;
+  if (moved_bytes) *moved_bytes = batch->bi.moved;
+  if (grid) *grid = batch->bi.grid;
+  if (wg_threads) *wg_threads = batch->bi.wg;
   return PYRIT_OK;
 }
 

@@ -79,4 +79,20 @@ int decode_entry(const pyrit_plan *plan, const int *erased, int n_erased,
                  std::shared_ptr<const DecodeEntry> *out);
 // Validates slice size S and slice pitch (0 is replaced by S).
 int check_slices(int w, size_t S, size_t *pitch);
+
+// Host image of a batch (work queue, pass descriptors, pointer and lift
+// tables) laid out for a device buffer at a given address.
+struct BatchImage {
+  std::vector<uint8_t> img;
+  size_t off_start = 0, off_pass = 0, off_item = 0;
+  uint32_t n_items = 0, n_passes = 0, total_waves = 0;
+  int grid = 0, wg = 128, mode = 0;
+  uint64_t moved = 0;
+};
+int batch_check_tune(pyrit_tune *t);
+int batch_resident_grid(const pyrit_tune &t, int *grid);
+int build_batch_image(const pyrit_batch_item *items, int n_items, const pyrit_tune &t,
+                      int resident_grid, uint64_t dev_base, BatchImage *bi);
+// Launch the batch kernel on an image already copied to `dev`.
+int launch_batch_image(const BatchImage &bi, void *dev, void *stream);
 }  // namespace pyrit

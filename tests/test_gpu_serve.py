@@ -1,0 +1,167 @@
+"""Served form: continuous batching of requests through the native request
+loop.  Each request's bytes in the mix must equal its bytes coded alone."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1709_00178_amd as P
+from paper_1709_00178_amd import serve
+from paper_1709_00178_amd import workloads as W
+from tests.gpu_util import sample_cols, torch_mod
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    torch = torch_mod()
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    oracle.build()
+    yield
+    torch.cuda.synchronize()
+
+
+def small_trace(n=240, rate=60000.0, seed=7, large_every=40):
+    """Uneven requests (blocks capped at 256 KiB) plus some k=10 m=4 GF(2^8)
+    requests of 2 MiB blocks, Poisson arrivals fast enough to batch."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t, out = 0.0, []
+    for i in range(n):
+        t += float(rng.exponential(1.0 / rate))
+        if i % large_every == large_every - 1:
+            st = W.Stripe(*W.RING_W8, k=10, m=4, B=2 * 1024 * 1024, stripe=i, seed=seed)
+            if i % 80 == 79:
+                st = dataclasses.replace(st, erased=(1, 5, 12))
+            out.append(W.Request(t, st, True))
+        else:
+            st = W.draw_stripe(rng, i, seed)
+            B = min(st.B, 256 * 1024) // 64 * 64
+            out.append(W.Request(t, dataclasses.replace(st, B=B), False))
+    return out
+
+
+def _pool_view(server, off, nbytes):
+    torch = torch_mod()
+    # a host copy of pool bytes [off, off + nbytes)
+    buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    import ctypes
+    lib = P._lib.lib()
+    rc = lib.pyrit_copy(ctypes.c_void_p(buf.data_ptr()), ctypes.c_void_p(server.pool_base + off),
+                        nbytes // 16 * 16, None)
+    assert rc == 0
+    torch.cuda.synchronize()
+    return buf.cpu().numpy()
+
+
+def _alone(plan, st, inputs, offs):
+    """Outputs of one request coded by itself (plain kernel, fresh buffers)."""
+    torch = torch_mod()
+    blocks = [None] * (st.k + st.m)
+    er = set(st.erased)
+    ins = [b for b in range(st.k + st.m) if b not in er][:st.k] if st.erased else list(range(st.k))
+    for b, o in zip(ins, offs):
+        blocks[b] = inputs.buf[o:o + st.block_len]
+    outs = list(st.erased) if st.erased else list(range(st.k, st.k + st.m))
+    for b in outs:
+        blocks[b] = torch.empty(st.block_len, dtype=torch.uint8, device="cuda")
+    if st.erased:
+        plan.decode(list(st.erased), blocks, st.S)
+    else:
+        plan.encode(blocks[:st.k], blocks[st.k:], st.S)
+    torch.cuda.synchronize()
+    return [blocks[b].cpu().numpy() for b in outs], ins
+
+
+def test_served_mix_equals_alone_and_oracle():
+    torch = torch_mod()
+    trace = small_trace()
+    inputs = serve.InputPool(256 << 20, key=0xC0FFEE)
+    plans = {}
+    prep = serve.prepare(trace, inputs, plans)
+    sv = serve.Server(pool_bytes=4 << 30, slots=3, release_outputs=False)
+    res, stats = sv.run(prep.array)
+    summ = serve.summarize(prep, res, stats)
+    # continuous batching: fewer launches than requests, and some launches
+    # enqueued while an earlier launch was still running
+    assert stats["launches"] < len(trace) and summ["mean_batch"] > 1.0, summ
+    launch_done = {}
+    for r in res:
+        launch_done[r["launch"]] = max(launch_done.get(r["launch"], 0.0), r["done_s"])
+    overlapped = sum(1 for r in res if any(l < r["launch"] and d > r["launch_s"]
+                                           for l, d in launch_done.items()))
+    assert overlapped > 0
+    assert (res["admit_s"] <= res["launch_s"]).all() and (res["launch_s"] <= res["done_s"]).all()
+    f_cache = {}
+    for i, (st, offs, large) in enumerate(prep.meta):
+        plan = plans[(st.w, st.n, st.p, st.k, st.m)]
+        alone, ins = _alone(plan, st, inputs, offs)
+        for q, blk in enumerate(alone):
+            mixed = _pool_view(sv, int(res[i]["out_offset"] + q * res[i]["out_stride"]), st.block_len)
+            assert np.array_equal(mixed[:st.block_len], blk), (i, q, st)
+        if i % 10 == 0:  # oracle on sampled columns
+            cols = sample_cols(st.S, 8, i)
+            f = f_cache.setdefault((st.w, st.p), oracle.Field(st.w, st.p))
+            G = plan.decode_matrix(list(st.erased))[1] if st.erased else plan.G
+            mini = []
+            for o in offs:
+                idx = (o + np.arange(st.w)[:, None] * st.S + cols[None, :]).reshape(-1)
+                mini.append(inputs.buf[torch.as_tensor(idx, device="cuda")].cpu().numpy())
+            want = f.encode(G, mini, len(cols))
+            for q, blk in enumerate(alone):
+                got = np.stack([blk[t * st.S + cols] for t in range(st.w)]).reshape(-1)
+                assert np.array_equal(got, want[q]), (i, q)
+    sv.close()
+    del torch
+
+
+def test_per_request_mode_same_bytes():
+    trace = small_trace(n=60, seed=11)
+    inputs = serve.InputPool(64 << 20, key=0xBEEF)
+    plans = {}
+    prep = serve.prepare(trace, inputs, plans)
+    a = serve.Server(pool_bytes=1 << 30, slots=2, release_outputs=False)
+    b = serve.Server(pool_bytes=1 << 30, slots=2, release_outputs=False, per_request=True)
+    ra, sa = a.run(prep.array)
+    rb, sb = b.run(prep.array)
+    assert sb["launches"] == len(trace) and sb["max_batch_seen"] == 1
+    for i, (st, offs, large) in enumerate(prep.meta):
+        n_out = len(st.erased) if st.erased else st.m
+        for q in range(n_out):
+            x = _pool_view(a, int(ra[i]["out_offset"] + q * ra[i]["out_stride"]), st.block_len)
+            y = _pool_view(b, int(rb[i]["out_offset"] + q * rb[i]["out_stride"]), st.block_len)
+            assert np.array_equal(x, y), (i, q)
+
+
+def test_admission_respects_the_pool_cap():
+    """A pool holding only a few requests' outputs: requests wait for space,
+    every request still completes, occupancy never exceeds the cap."""
+    trace = small_trace(n=120, rate=200000.0, seed=13, large_every=10)
+    inputs = serve.InputPool(64 << 20, key=0xABC)
+    plans = {}
+    prep = serve.prepare(trace, inputs, plans)
+    biggest = max(st.block_len * (len(st.erased) if st.erased else st.m) for st, _, _ in prep.meta)
+    cap = int(2.5 * (biggest + 4 * 4352)) // 256 * 256
+    sv = serve.Server(pool_bytes=cap, slots=2, release_outputs=True)
+    res, stats = sv.run(prep.array)
+    assert stats["admission_waits"] > 0
+    assert 0 < stats["peak_pool_bytes"] <= cap
+    assert (res["done_s"] > 0).all()
+
+
+def test_pool_too_small_is_an_error():
+    """Outputs kept and a pool smaller than their sum: the loop reports that
+    the head request can never be admitted instead of waiting forever."""
+    trace = small_trace(n=30, seed=17, large_every=10)
+    inputs = serve.InputPool(32 << 20, key=1)
+    plans = {}
+    prep = serve.prepare(trace, inputs, plans)
+    total = sum((len(st.erased) if st.erased else st.m) * (st.block_len + 4352)
+                for st, _, _ in prep.meta)
+    cap = 20 << 20
+    assert total > cap
+    sv = serve.Server(pool_bytes=cap, slots=1, release_outputs=False)
+    with pytest.raises(P.PyritError) as e:
+        sv.run(prep.array)
+    assert e.value.code == -12
