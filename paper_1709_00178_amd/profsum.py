@@ -1,0 +1,120 @@
+"""Summaries of rocprofv3 CSV output for the committed profiles.
+
+    python -m paper_1709_00178_amd.profsum stats  <run_kernel_stats.csv>  --cmd "..." > out.md
+    python -m paper_1709_00178_amd.profsum traffic --fetch <dir> --write <dir> --kernel NAME \\
+        --copy-bytes N --record KEY [--algorithmic BYTES] --cmd "..." > out.md
+
+`traffic` turns per-dispatch FETCH_SIZE and WRITE_SIZE (KiB) of a kernel
+into HBM bytes per launch, each scaled by what the same counter reads for the
+library's copy kernel moving a known number of bytes (half read, half
+written), and updates profiles/traffic.json with the kernel-source hash the
+benchmark checks before reporting the figure.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import statistics
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+KERNEL_SOURCES = ["paper_1709_00178_amd/csrc/ring_kernels.hpp",
+                  "paper_1709_00178_amd/csrc/plain_impl.hpp",
+                  "paper_1709_00178_amd/csrc/batch.hip"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stats_table(path: str) -> str:
+    rows = list(csv.DictReader(open(path)))
+    out = ["| kernel | calls | avg us | min us | max us | total % |",
+           "|---|---:|---:|---:|---:|---:|"]
+    for r in rows:
+        out.append(f"| `{r['Name']}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                   f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
+                   f"{float(r['Percentage']):.1f} |")
+    return "\n".join(out)
+
+
+def counter_means(directory: str, counter: str) -> dict:
+    """Mean value of `counter` per kernel name over its dispatches."""
+    files = glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)
+    vals: dict = {}
+    for fn in files:
+        for r in csv.DictReader(open(fn)):
+            if r["Counter_Name"] == counter:
+                vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return {k: (statistics.fmean(v), len(v)) for k, v in vals.items()}
+
+
+def find(d: dict, needle: str):
+    hits = [k for k in d if needle in k]
+    if len(hits) != 1:
+        raise SystemExit(f"kernel '{needle}' matched {hits}")
+    return d[hits[0]], hits[0]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="what", required=True)
+    a = sub.add_parser("stats")
+    a.add_argument("csv")
+    a.add_argument("--cmd", required=True)
+    b = sub.add_parser("traffic")
+    b.add_argument("--fetch", required=True)
+    b.add_argument("--write", required=True)
+    b.add_argument("--kernel", required=True)
+    b.add_argument("--copy-kernel", default="copy_kernel")
+    b.add_argument("--copy-bytes", type=int, required=True)
+    b.add_argument("--record", required=True)
+    b.add_argument("--algorithmic", type=int, default=0)
+    b.add_argument("--cmd", required=True)
+    args = ap.parse_args()
+    if args.what == "stats":
+        print(f"Command: `{args.cmd}`\n")
+        print(stats_table(args.csv))
+        return
+    fetch = counter_means(args.fetch, "FETCH_SIZE")
+    write = counter_means(args.write, "WRITE_SIZE")
+    (kf, nf), name = find(fetch, args.kernel)
+    (kw, nw), _ = find(write, args.kernel)
+    (cf, _), _ = find(fetch, args.copy_kernel)
+    (cw, _), _ = find(write, args.copy_kernel)
+    half_kib = args.copy_bytes / 2 / 1024
+    f_scale, w_scale = half_kib / cf, half_kib / cw
+    traffic = int(round((kf * f_scale + kw * w_scale) * 1024))
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    rec = json.load(open(path)) if os.path.exists(path) else {}
+    rec[args.record] = {"kernel": name, "kernel_hash": kernel_hash(), "bytes_per_launch": traffic,
+                        "fetch_kib": round(kf, 1), "write_kib": round(kw, 1),
+                        "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
+                        "dispatches": [nf, nw], "command": args.cmd}
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=1, sort_keys=True)
+        f.write("\n")
+    print(f"Command: `{args.cmd}` (one `--pmc FETCH_SIZE` run, one `--pmc WRITE_SIZE` run)\n")
+    print(f"Kernel: `{name}`\n")
+    print("| quantity | value |\n|---|---:|")
+    print(f"| FETCH_SIZE per dispatch (KiB, mean of {nf}) | {kf:.1f} |")
+    print(f"| WRITE_SIZE per dispatch (KiB, mean of {nw}) | {kw:.1f} |")
+    print(f"| copy kernel FETCH_SIZE (KiB) for {half_kib:.0f} KiB read | {cf:.1f} |")
+    print(f"| copy kernel WRITE_SIZE (KiB) for {half_kib:.0f} KiB written | {cw:.1f} |")
+    print(f"| FETCH scale (true / counted) | {f_scale:.4f} |")
+    print(f"| WRITE scale (true / counted) | {w_scale:.4f} |")
+    print(f"| HBM bytes per launch (scaled) | {traffic} |")
+    if args.algorithmic:
+        print(f"| algorithmic bytes per launch | {args.algorithmic} |")
+        print(f"| traffic / algorithmic | {traffic / args.algorithmic:.4f} |")
+
+
+if __name__ == "__main__":
+    main()
