@@ -212,6 +212,11 @@ typedef struct {
   int tile_bytes;   /* persistent modes: column bytes per item; 0 = library choice */
   int grid;         /* persistent modes: resident workgroups; 0 = CUs x occupancy */
   int wg_threads;   /* 64, 128 or 256 threads per workgroup; 0 = 128 */
+  int xcd_order;    /* grid mode, 0 or 1.  Workgroups are dealt round-robin
+                       over the 8 XCDs; with 1 the workgroup-to-item map is
+                       permuted so that each XCD codes a contiguous eighth of
+                       the queue (0: workgroup i codes item i).  Persistent
+                       modes ignore it. */
 } pyrit_tune;
 
 typedef struct pyrit_batch pyrit_batch;

@@ -173,16 +173,21 @@ class Plan:
 
 
 class Batch:
-    """Many stripes coded by one persistent-kernel launch (a hipGraph replay).
+    """Many stripes coded by one batch-kernel launch.
 
     ``items``: iterable of ``(plan, erased, blocks, S)`` or ``(plan, erased,
     blocks, S, pitch)``; ``erased`` empty for an encode; ``blocks`` holds
     k + m device buffers (entries that are neither inputs nor outputs may be
-    None).
+    None).  ``launch`` is the form `run` uses: ``"graph"`` replays the
+    instantiated hipGraph (`launch`), ``"direct"`` dispatches the same kernel
+    with the same arguments (`launch_direct`).
     """
 
     def __init__(self, items, mode: str = "grid", tile_bytes: int = 0, grid: int = 0,
-                 wg_threads: int = 0):
+                 wg_threads: int = 0, xcd_order: int = 0, launch: str = "graph"):
+        if launch not in ("graph", "direct"):
+            raise ValueError("launch must be 'graph' or 'direct'")
+        self.launch_form = launch
         from ._lib import BATCH_MODES, BatchItem, Tune
         items = list(items)
         self._keep = []
@@ -204,7 +209,7 @@ class Batch:
         if mode not in BATCH_MODES:
             raise ValueError(f"mode must be one of {sorted(BATCH_MODES)}")
         self.mode = mode
-        tune = Tune(BATCH_MODES[mode], tile_bytes, grid, wg_threads)
+        tune = Tune(BATCH_MODES[mode], tile_bytes, grid, wg_threads, xcd_order)
         h = ctypes.c_void_p()
         _check(lib().pyrit_batch_create(arr, len(items), ctypes.byref(tune), ctypes.byref(h)))
         self._h = h
@@ -214,6 +219,13 @@ class Batch:
 
     def launch_direct(self, stream=None) -> None:
         _check(lib().pyrit_batch_launch_direct(self._h, _stream_handle(stream)))
+
+    def run(self, stream=None) -> None:
+        """Launch in the form chosen at construction."""
+        if self.launch_form == "graph":
+            self.launch(stream)
+        else:
+            self.launch_direct(stream)
 
     def info(self) -> dict:
         np_, ni, gr, wg = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()

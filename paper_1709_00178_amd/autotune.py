@@ -1,8 +1,9 @@
 """Autotuner for batched launches.
 
 For a batch it times a small set of executors (queue drain mode, threads per
-workgroup, tile width) with HIP events on the caller's stream and keeps the
-fastest.  Results are cached per batch signature (rings, code shapes, slice
+workgroup, tile width, XCD-contiguous item order) in both launch forms (hipGraph
+replay and direct dispatch) with HIP events on the caller's stream and keeps
+the fastest.  Results are cached per batch signature (rings, code shapes, slice
 size class, encode/decode mix) in memory and in a JSON file
 (``PYRIT_AUTOTUNE_CACHE``, default ``~/.cache/pyrit_mi355x_autotune.json``),
 so a signature is only tuned once per machine.
@@ -23,6 +24,9 @@ CANDIDATES = [
     {"mode": "grid", "wg_threads": 64},
     {"mode": "grid", "wg_threads": 128},
     {"mode": "grid", "wg_threads": 256},
+    {"mode": "grid", "wg_threads": 64, "xcd_order": 1},
+    {"mode": "grid", "wg_threads": 128, "xcd_order": 1},
+    {"mode": "grid", "wg_threads": 256, "xcd_order": 1},
     {"mode": "queue", "wg_threads": 256, "tile_bytes": 0},
     {"mode": "queue", "wg_threads": 256, "tile_bytes": 4096},
     {"mode": "static", "wg_threads": 128, "tile_bytes": 0},
@@ -73,20 +77,21 @@ def signature(items) -> str:
     if n == 0:
         return "empty"
     return "|".join([
-        ",".join(f"{w}/{nn}/{p:x}" for w, nn, p in sorted(rings)),
+        "v2", ",".join(f"{w}/{nn}/{p:x}" for w, nn, p in sorted(rings)),
         f"k{min(ks)}-{max(ks)}", f"o{min(outs)}-{max(outs)}",
         f"s{int(math.log2(min(sizes)))}-{int(math.log2(max(sizes)))}",
         f"d{round(10 * dec / n)}", f"n{int(math.log2(n))}",
     ])
 
 
-def time_batch(batch, stream, reps: int = 5) -> float:
+def time_batch(batch, stream, reps: int = 5, form: str = "graph") -> float:
     import torch
-    batch.launch(stream)
+    fn = batch.launch if form == "graph" else batch.launch_direct
+    fn(stream)
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record(stream)
     for _ in range(reps):
-        batch.launch(stream)
+        fn(stream)
     b.record(stream)
     b.synchronize()
     return a.elapsed_time(b) / reps
@@ -110,12 +115,14 @@ def tuned_batch(items, stream=None, candidates=None, retune: bool = False, log=N
     best, best_ms = None, float("inf")
     for cand in candidates or CANDIDATES:
         b = Batch(items, **cand)
-        ms = time_batch(b, stream)
-        timings.append((dict(cand), ms))
-        if log:
-            log(f"autotune {sig}: {cand} {ms:.4f} ms")
-        if ms < best_ms:
-            best, best_ms = cand, ms
+        for form in ("graph", "direct"):
+            c = dict(cand, launch=form)
+            ms = time_batch(b, stream, form=form)
+            timings.append((c, ms))
+            if log:
+                log(f"autotune {sig}: {c} {ms:.4f} ms")
+            if ms < best_ms:
+                best, best_ms = c, ms
         b.close()
     with _lock:
         _mem[sig] = dict(best)

@@ -30,7 +30,8 @@ namespace pyrit {
 // loads.
 #define AS4 __attribute__((address_space(4)))
 
-constexpr int kGroups = 8;  // sub-queues (one per XCD-sized group of workgroups)
+constexpr int kGroups = 8;     // sub-queues (one per XCD-sized group of workgroups)
+constexpr uint32_t kXcds = 8;  // XCDs of an MI355X
 
 struct PassDesc {
   uint64_t in_tab;    // k input block pointers
@@ -119,12 +120,21 @@ __device__ __forceinline__ void code_item(const AS4 PassDesc *passes, const AS4 
 // numbered pass by pass, so the workgroup finds its pass by binary search
 // over the per-pass start indices (a small array every workgroup reads, hot
 // in the scalar cache) instead of loading a per-item record.
-template <int WG>
+//
+// The dispatcher deals workgroups round-robin over the XCDs (workgroup i to
+// XCD i mod 8).  With XCD_ORDER the workgroup-to-item map is permuted so that
+// each XCD walks its own contiguous eighth of the queue.
+template <int WG, bool XCD_ORDER>
 __global__ __launch_bounds__(WG) void batch_grid_kernel(const BatchArgs a) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const AS4 uint32_t *starts = (const AS4 uint32_t *)a.starts;
-  const uint32_t b = blockIdx.x;
+  uint32_t b = blockIdx.x;
+  if constexpr (XCD_ORDER) {
+    const uint32_t x = b % kXcds, i = b / kXcds;
+    const uint32_t per = gridDim.x / kXcds, rem = gridDim.x % kXcds;
+    b = x < rem ? x * (per + 1u) + i : rem * (per + 1u) + (x - rem) * per + i;
+  }
   uint32_t lo = 0, hi = a.n_passes;
   while (hi - lo > 1) {
     const uint32_t mid = (lo + hi) >> 1;
@@ -190,11 +200,11 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(5))) void ba
   }
 }
 
-static const void *grid_fn(int wg) {
+static const void *grid_fn(int wg, bool xcd) {
   switch (wg) {
-    case 64: return (const void *)batch_grid_kernel<64>;
-    case 128: return (const void *)batch_grid_kernel<128>;
-    case 256: return (const void *)batch_grid_kernel<256>;
+    case 64: return xcd ? (const void *)batch_grid_kernel<64, true> : (const void *)batch_grid_kernel<64, false>;
+    case 128: return xcd ? (const void *)batch_grid_kernel<128, true> : (const void *)batch_grid_kernel<128, false>;
+    case 256: return xcd ? (const void *)batch_grid_kernel<256, true> : (const void *)batch_grid_kernel<256, false>;
     default: return nullptr;
   }
 }
@@ -288,8 +298,8 @@ uint64_t item_cost(const HostPass &hp, const WorkItem &wi) {
   return (uint64_t)(hp.k + hp.nout) * hp.w * (wi.col1 - wi.col0) + (uint64_t)hp.k * hp.w * 1024u;
 }
 
-const void *kernel_fn(int mode, int wg) {
-  return mode == kModeGrid ? grid_fn(wg) : persistent_fn(wg, mode);
+const void *kernel_fn(int mode, int wg, int xcd_order) {
+  return mode == kModeGrid ? grid_fn(wg, xcd_order != 0) : persistent_fn(wg, mode);
 }
 
 }  // namespace
@@ -298,6 +308,7 @@ namespace pyrit {
 
 int batch_check_tune(pyrit_tune *t) {
   if (t->mode < 0 || t->mode > 2 || t->tile_bytes < 0 || t->grid < 0) return PYRIT_EINVAL;
+  if (t->xcd_order != 0 && t->xcd_order != 1) return PYRIT_EINVAL;
   if (t->wg_threads == 0) t->wg_threads = 128;
   if (t->wg_threads != 64 && t->wg_threads != 128 && t->wg_threads != 256) return PYRIT_EINVAL;
   return PYRIT_OK;
@@ -308,7 +319,7 @@ int batch_resident_grid(const pyrit_tune &t, int *grid) {
   if (hipGetDevice(&dev) != hipSuccess) return PYRIT_EHIP;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return PYRIT_EHIP;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel_fn(t.mode, t.wg_threads),
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel_fn(t.mode, t.wg_threads, 0),
                                                    t.wg_threads, 0) != hipSuccess)
     return PYRIT_EHIP;
   int g = t.grid ? t.grid : std::max(1, per_cu * ncu);
@@ -444,6 +455,7 @@ int build_batch_image(const pyrit_batch_item *items, int n_items, const pyrit_tu
   bi->total_waves = total_waves;
   bi->mode = t.mode;
   bi->wg = t.wg_threads;
+  bi->xcd_order = t.xcd_order;
   bi->grid = persistent ? grid : (int)work.size();
   return PYRIT_OK;
 }
@@ -464,7 +476,7 @@ int launch_batch_image(const BatchImage &bi, void *dev, void *stream) {
   if (bi.n_items == 0) return PYRIT_OK;
   BatchArgs a = image_args(bi, dev);
   void *kargs[] = {&a};
-  return hipLaunchKernel(kernel_fn(bi.mode, bi.wg), dim3(bi.grid), dim3(bi.wg), kargs, 0,
+  return hipLaunchKernel(kernel_fn(bi.mode, bi.wg, bi.xcd_order), dim3(bi.grid), dim3(bi.wg), kargs, 0,
                          (hipStream_t)stream) == hipSuccess
              ? PYRIT_OK
              : PYRIT_EHIP;
@@ -522,7 +534,7 @@ int pyrit_batch_create(const pyrit_batch_item *items, int n_items, const pyrit_t
   if (hipGraphCreate(&b->graph, 0) != hipSuccess) return PYRIT_EHIP;
   hipKernelNodeParams kp{};
   void *kargs[] = {&b->args};
-  kp.func = const_cast<void *>(kernel_fn(b->bi.mode, b->bi.wg));
+  kp.func = const_cast<void *>(kernel_fn(b->bi.mode, b->bi.wg, b->bi.xcd_order));
   kp.gridDim = dim3(b->bi.grid);
   kp.blockDim = dim3(b->bi.wg);
   kp.sharedMemBytes = 0;

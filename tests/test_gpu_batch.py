@@ -74,18 +74,19 @@ def test_batch_single_stripe_every_shape():
     bufs, items = _build([st], plans, arena)
     host = W.host_blocks(st)
     want = oracle.Field(st.w, st.p).encode(plans.get(st).G, host, st.S, nthreads=4)
+    shapes = [("grid", 0, 0), ("grid", 0, 1), ("queue", 0, 0), ("queue", 512, 0),
+              ("queue", 4096, 0), ("static", 0, 0), ("static", 512, 0), ("static", 4096, 0)]
     for wg in [64, 128, 256]:
-        for mode in ["grid", "queue", "static"]:
-            for tile in ([0] if mode == "grid" else [0, 512, 4096]):
-                b = P.Batch(items, mode=mode, tile_bytes=tile, wg_threads=wg)
-                for launch in [b.launch, b.launch_direct, b.launch]:
-                    _clear_outputs(bufs, 0xEE)
-                    launch()
-                    sync()
-                    for i in range(st.m):
-                        got = to_host(bufs[0][0][st.k + i])
-                        assert np.array_equal(got, want[i]), (wg, mode, tile, i)
-                b.close()
+        for mode, tile, xcd in shapes:
+            b = P.Batch(items, mode=mode, tile_bytes=tile, wg_threads=wg, xcd_order=xcd)
+            for launch in [b.launch, b.launch_direct, b.launch, b.run]:
+                _clear_outputs(bufs, 0xEE)
+                launch()
+                sync()
+                for i in range(st.m):
+                    got = to_host(bufs[0][0][st.k + i])
+                    assert np.array_equal(got, want[i]), (wg, mode, tile, xcd, i)
+            b.close()
 
 
 @pytest.mark.parametrize("mode", ["grid", "queue", "static"])
@@ -104,13 +105,13 @@ def test_batch_graph_replays_with_eager_work_between(mode):
         _check_stripes(stripes, bufs, plans, ncols=8, seed=rep)
 
 
-@pytest.mark.parametrize("mode", ["grid", "queue", "static"])
-def test_c2_all_stripes_one_launch(mode):
+@pytest.mark.parametrize("mode,xcd", [("grid", 0), ("grid", 1), ("queue", 0), ("static", 0)])
+def test_c2_all_stripes_one_launch(mode, xcd):
     stripes = W.c2()
     plans = PlanCache()
     arena = Arena(sum(stripe_bytes_needed(s) for s in stripes) + 4096)
     bufs, items = _build(stripes, plans, arena)
-    b = P.Batch(items, mode=mode)
+    b = P.Batch(items, mode=mode, xcd_order=xcd)
     info = b.info()
     assert info["passes"] == 256
     assert info["moved_bytes"] == sum(s.moved_bytes() for s in stripes)
@@ -119,15 +120,15 @@ def test_c2_all_stripes_one_launch(mode):
     _check_stripes(stripes, bufs, plans, ncols=12)
 
 
-@pytest.mark.parametrize("mode", ["grid", "queue", "static"])
-def test_c3_all_4096_uneven_stripes_one_launch(mode):
+@pytest.mark.parametrize("mode,xcd", [("grid", 0), ("grid", 1), ("queue", 0), ("static", 0)])
+def test_c3_all_4096_uneven_stripes_one_launch(mode, xcd):
     """The uneven batch: w in {4,8,10}, k in [4,16], m in [2,4], 4 KiB..4 MiB
     blocks, 30% decodes, all in one launch."""
     stripes = W.c3()
     plans = PlanCache()
     arena = Arena(sum(stripe_bytes_needed(s) for s in stripes) + 4096)
     bufs, items = _build(stripes, plans, arena)
-    b = P.Batch(items, mode=mode)
+    b = P.Batch(items, mode=mode, xcd_order=xcd)
     info = b.info()
     assert info["moved_bytes"] == sum(s.moved_bytes() for s in stripes)
     _clear_outputs(bufs, 0x77)
@@ -187,8 +188,13 @@ def test_batch_errors():
     with pytest.raises(P.PyritError) as e:
         P.Batch([(plan, [], blocks, st.S)], wg_threads=96)
     assert e.value.code == -1
+    with pytest.raises(P.PyritError) as e:
+        P.Batch([(plan, [], blocks, st.S)], xcd_order=2)
+    assert e.value.code == -1
     with pytest.raises(ValueError):
         P.Batch([(plan, [], blocks, st.S)], mode="fifo")
+    with pytest.raises(ValueError):
+        P.Batch([(plan, [], blocks, st.S)], launch="stream")
     empty = P.Batch([])
     empty.launch()
     sync()
