@@ -18,7 +18,12 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pyrit_oracle.c")
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# PYRIT_ORACLE_MUTANT=n builds and loads a copy with planted mistake n (see
+# OR_MUTANT in the C source) under PYRIT_ORACLE_DIR; only the mutant test
+# sets them, to show that the pins reject every planted mistake.
+_MUTANT = int(os.environ.get("PYRIT_ORACLE_MUTANT", "0"))
+_LIB_PATH = (os.path.join(_HERE, "liboracle.so") if _MUTANT == 0 else
+             os.path.join(os.environ["PYRIT_ORACLE_DIR"], f"liboracle_m{_MUTANT}.so"))
 
 ERRORS = {0: "ok", -1: "invalid argument", -2: "modulus not irreducible",
           -3: "code too long for the field", -4: "singular matrix",
@@ -28,7 +33,7 @@ ERRORS = {0: "ok", -1: "invalid argument", -2: "modulus not irreducible",
 def build(verbose: bool = False) -> str:
     """Compile the oracle with gcc (-O2, OpenMP, no intrinsics)."""
     cmd = ["gcc", "-O2", "-fopenmp", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
-           _SRC, "-o", _LIB_PATH + ".tmp"]
+           f"-DOR_MUTANT={_MUTANT}", _SRC, "-o", _LIB_PATH + ".tmp"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

@@ -36,10 +36,18 @@
  * same map, closed forms (XOR parity, multiply by x^s), and recovery from
  * every erasure pattern.  The parity bytes of the paper's own generator are
  * "parity unpinned": the paper prints no codeword and no matrix.
+ *
+ * OR_MUTANT (default 0) plants one known mistake per nonzero value, so that
+ * tests/test_oracle_mutants.py can show each of them is caught by the pins.
+ * A normal build compiles every mutant branch away.
  */
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+#ifndef OR_MUTANT
+#define OR_MUTANT 0
+#endif
 
 #define OR_OK 0
 #define OR_EINVAL -1
@@ -99,7 +107,7 @@ int or_field_create(int w, uint32_t p, or_field **out) {
     f->p = p;
     f->q1 = (1u << w) - 1u;
     f->exp_t = (uint32_t *)malloc(sizeof(uint32_t) * 2u * (f->q1 + 1u));
-    f->log_t = (uint32_t *)malloc(sizeof(uint32_t) * (f->q1 + 1u));
+    f->log_t = (uint32_t *)calloc(f->q1 + 1u, sizeof(uint32_t));
     if (!f->exp_t || !f->log_t) { or_field_free(f); return OR_ENOMEM; }
     if (w == 1) {  /* GF(2): the group is trivial, 1 generates it */
         f->g = 1;
@@ -116,7 +124,7 @@ int or_field_create(int w, uint32_t p, or_field **out) {
             ++ord;
             if (v == 0) { ord = f->q1 + 1; break; }  /* zero divisor */
         }
-        if (ord == f->q1) { f->g = g; break; }
+        if (ord == f->q1 || (OR_MUTANT == 1 && g == 2)) { f->g = g; break; }
     }
     if (f->g == 0) { or_field_free(f); return OR_ENOTIRRED; }
     uint32_t v = 1;
@@ -133,7 +141,7 @@ uint32_t or_field_generator(const or_field *f) { return f->g; }
 
 uint32_t or_mul(const or_field *f, uint32_t a, uint32_t b) {
     if (a == 0 || b == 0) return 0;
-    return f->exp_t[f->log_t[a] + f->log_t[b]];
+    return f->exp_t[f->log_t[a] + f->log_t[b] + (OR_MUTANT == 2)];
 }
 
 void or_mul_many(const or_field *f, const uint32_t *a, const uint32_t *b, uint32_t *out, size_t n) {
@@ -142,7 +150,7 @@ void or_mul_many(const or_field *f, const uint32_t *a, const uint32_t *b, uint32
 
 uint32_t or_inv(const or_field *f, uint32_t a) {
     if (a == 0) return 0;  /* callers never invert zero */
-    return f->exp_t[(f->q1 - f->log_t[a]) % f->q1];
+    return f->exp_t[(f->q1 - f->log_t[a] + (OR_MUTANT == 3)) % f->q1];
 }
 
 /* Parity part of the systematic generator: C[i][j] = 1 / (i + (m + j)). */
@@ -151,14 +159,15 @@ int or_cauchy(const or_field *f, int k, int m, uint16_t *C) {
     if ((uint32_t)(k + m) > f->q1 + 1u) return OR_ETOOLONG;
     for (int i = 0; i < m; ++i)
         for (int j = 0; j < k; ++j)
-            C[i * k + j] = (uint16_t)or_inv(f, (uint32_t)i ^ (uint32_t)(m + j));
+            C[i * k + j] = (uint16_t)or_inv(f, (uint32_t)i ^ (uint32_t)(OR_MUTANT == 4 ? j + 1 : m + j));
     return OR_OK;
 }
 
 /* Symbol (o, b) of a bit-sliced block: bit t is bit b of byte o of slice t. */
 static uint32_t get_symbol(const uint8_t *blk, int w, size_t S, size_t o, int b) {
     uint32_t u = 0;
-    for (int t = 0; t < w; ++t) u |= (uint32_t)((blk[(size_t)t * S + o] >> b) & 1u) << t;
+    for (int t = 0; t < w; ++t)
+        u |= (uint32_t)((blk[(size_t)(OR_MUTANT == 5 ? w - 1 - t : t) * S + o] >> b) & 1u) << t;
     return u;
 }
 
@@ -187,7 +196,8 @@ static void matvec_blocks(const or_field *f, int rows, int cols, const uint16_t 
             for (int j = 0; j < cols; ++j) u[j] = get_symbol(in[j], w, S, o, b);
             for (int i = 0; i < rows; ++i) {
                 uint32_t acc = 0;
-                for (int j = 0; j < cols; ++j) acc ^= or_mul(f, M[i * cols + j], u[j]);
+                for (int j = 0; j < cols - (OR_MUTANT == 6 && cols > 1); ++j)
+                    acc ^= or_mul(f, M[i * cols + j], u[j]);
                 put_symbol(out[i], w, S, o, b, acc);
             }
         }
@@ -221,7 +231,7 @@ int or_invert(const or_field *f, int k, uint16_t *A) {
         for (int r = c; r < k; ++r)
             if (A[r * k + c]) { piv = r; break; }
         if (piv < 0) { free(I); return OR_ESINGULAR; }
-        if (piv != c) {
+        if (piv != c && OR_MUTANT != 7) {
             for (int x = 0; x < k; ++x) {
                 uint16_t t = A[c * k + x]; A[c * k + x] = A[piv * k + x]; A[piv * k + x] = t;
                 t = I[c * k + x]; I[c * k + x] = I[piv * k + x]; I[piv * k + x] = t;
@@ -276,7 +286,8 @@ int or_decode(const or_field *f, int k, int m, const uint16_t *C,
     for (int r = 0; r < k; ++r) {
         int g = surv[r];
         for (int c = 0; c < k; ++c)
-            A[r * k + c] = (g < k) ? (uint16_t)(g == c) : C[(g - k) * k + c];
+            A[r * k + c] = (g < k) ? (uint16_t)(g == c)
+                                   : C[(g - k) * k + (OR_MUTANT == 9 ? k - 1 - c : c)];
     }
     int rc = or_invert(f, k, A);
     if (rc != OR_OK) { free(A); return rc; }
@@ -292,7 +303,7 @@ int or_decode(const or_field *f, int k, int m, const uint16_t *C,
     const uint8_t *dat[64];
     for (int j = 0; j < k; ++j) dat[j] = blocks[j];
     for (int i = 0; i < m; ++i) {
-        if (!is_erased[k + i]) continue;
+        if (!is_erased[k + i] || OR_MUTANT == 8) continue;
         uint8_t *outp[1] = {blocks[k + i]};
         matvec_blocks(f, 1, k, C + (size_t)i * k, dat, outp, S, o0, o1, nthreads);
     }
