@@ -217,6 +217,11 @@ typedef struct {
                        permuted so that each XCD codes a contiguous eighth of
                        the queue (0: workgroup i codes item i).  Persistent
                        modes ignore it. */
+  int split_k;      /* grid mode: waves sharing one column chunk, each coding
+                       every split_k-th input block, partial sums combined in
+                       LDS before the stores: 1, or 2 (128-thread workgroups
+                       only); 0 = 2 for 128-thread grid workgroups, else 1.
+                       Persistent modes take 0 or 1. */
 } pyrit_tune;
 
 typedef struct pyrit_batch pyrit_batch;

@@ -184,7 +184,8 @@ class Batch:
     """
 
     def __init__(self, items, mode: str = "grid", tile_bytes: int = 0, grid: int = 0,
-                 wg_threads: int = 0, xcd_order: int = 0, launch: str = "graph"):
+                 wg_threads: int = 0, xcd_order: int = 0, split_k: int = 0,
+                 launch: str = "graph"):
         if launch not in ("graph", "direct"):
             raise ValueError("launch must be 'graph' or 'direct'")
         self.launch_form = launch
@@ -209,7 +210,7 @@ class Batch:
         if mode not in BATCH_MODES:
             raise ValueError(f"mode must be one of {sorted(BATCH_MODES)}")
         self.mode = mode
-        tune = Tune(BATCH_MODES[mode], tile_bytes, grid, wg_threads, xcd_order)
+        tune = Tune(BATCH_MODES[mode], tile_bytes, grid, wg_threads, xcd_order, split_k)
         h = ctypes.c_void_p()
         _check(lib().pyrit_batch_create(arr, len(items), ctypes.byref(tune), ctypes.byref(h)))
         self._h = h

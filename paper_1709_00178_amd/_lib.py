@@ -62,7 +62,7 @@ class BatchItem(ctypes.Structure):
 class Tune(ctypes.Structure):
     """pyrit_tune"""
     _fields_ = [("mode", c_int), ("tile_bytes", c_int), ("grid", c_int),
-                ("wg_threads", c_int), ("xcd_order", c_int)]
+                ("wg_threads", c_int), ("xcd_order", c_int), ("split_k", c_int)]
 
 
 BATCH_MODES = {"grid": 0, "queue": 1, "static": 2}

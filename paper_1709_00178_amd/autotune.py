@@ -1,7 +1,7 @@
 """Autotuner for batched launches.
 
 For a batch it times a small set of executors (queue drain mode, threads per
-workgroup, tile width, XCD-contiguous item order) in both launch forms (hipGraph
+workgroup, split-K, tile width, XCD-contiguous item order) in both launch forms (hipGraph
 replay and direct dispatch) with HIP events on the caller's stream and keeps
 the fastest.  Results are cached per batch signature (rings, code shapes, slice
 size class, encode/decode mix) in memory and in a JSON file
@@ -21,12 +21,14 @@ import threading
 from . import Batch
 
 CANDIDATES = [
-    {"mode": "grid", "wg_threads": 64},
-    {"mode": "grid", "wg_threads": 128},
-    {"mode": "grid", "wg_threads": 256},
-    {"mode": "grid", "wg_threads": 64, "xcd_order": 1},
-    {"mode": "grid", "wg_threads": 128, "xcd_order": 1},
-    {"mode": "grid", "wg_threads": 256, "xcd_order": 1},
+    {"mode": "grid", "wg_threads": 128, "split_k": 2},
+    {"mode": "grid", "wg_threads": 128, "split_k": 2, "xcd_order": 1},
+    {"mode": "grid", "wg_threads": 64, "split_k": 1},
+    {"mode": "grid", "wg_threads": 128, "split_k": 1},
+    {"mode": "grid", "wg_threads": 256, "split_k": 1},
+    {"mode": "grid", "wg_threads": 64, "split_k": 1, "xcd_order": 1},
+    {"mode": "grid", "wg_threads": 128, "split_k": 1, "xcd_order": 1},
+    {"mode": "grid", "wg_threads": 256, "split_k": 1, "xcd_order": 1},
     {"mode": "queue", "wg_threads": 256, "tile_bytes": 0},
     {"mode": "queue", "wg_threads": 256, "tile_bytes": 4096},
     {"mode": "static", "wg_threads": 128, "tile_bytes": 0},
@@ -77,7 +79,7 @@ def signature(items) -> str:
     if n == 0:
         return "empty"
     return "|".join([
-        "v2", ",".join(f"{w}/{nn}/{p:x}" for w, nn, p in sorted(rings)),
+        "v3", ",".join(f"{w}/{nn}/{p:x}" for w, nn, p in sorted(rings)),
         f"k{min(ks)}-{max(ks)}", f"o{min(outs)}-{max(outs)}",
         f"s{int(math.log2(min(sizes)))}-{int(math.log2(max(sizes)))}",
         f"d{round(10 * dec / n)}", f"n{int(math.log2(n))}",

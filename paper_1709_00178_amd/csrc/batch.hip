@@ -62,7 +62,18 @@ struct BatchArgs {
 // outputs), so one kernel holds all rings at five waves per SIMD.
 constexpr int kBatchV[kNumRings] = {2, 1, 1, 1, 1};
 
-__host__ __device__ constexpr uint32_t chunk_bytes(int ring) { return 64u * 4u * kBatchV[ring]; }
+// kBatchV packed four bits per ring, so a run-time ring id maps to its lane
+// width with a shift instead of a table load.
+constexpr uint32_t pack_batch_v() {
+  uint32_t b = 0;
+  for (int i = 0; i < kNumRings; ++i) b |= (uint32_t)kBatchV[i] << (4 * i);
+  return b;
+}
+constexpr uint32_t kBatchVBits = pack_batch_v();
+
+__host__ __device__ constexpr uint32_t chunk_bytes(int ring) {
+  return 64u * 4u * ((kBatchVBits >> (4 * ring)) & 15u);
+}
 
 struct TableSrc {
   const AS4 uint64_t *in_tab;
@@ -79,11 +90,17 @@ struct TableSrc {
   __device__ const uint8_t *in(int j) const { return (const uint8_t *)in_tab[j]; }
   __device__ uint8_t *out(int r) const { return (uint8_t *)out_tab[r]; }
   __device__ uint32_t lift(int j, int r) const { return lift_tab[j * kMaxOut + r]; }
+  __device__ dev::u32x4 lift4(int j) const { return *(const AS4 dev::u32x4 *)(lift_tab + j * kMaxOut); }
 };
 
+__device__ __forceinline__ TableSrc table_src(const PassDesc &d) {
+  return TableSrc{(const AS4 uint64_t *)d.in_tab, (const AS4 uint64_t *)d.out_tab,
+                  (const AS4 uint32_t *)d.lift_tab, (int)d.k, d.S, d.pitch, (int)d.nout};
+}
+
 __device__ __forceinline__ TableSrc table_src(const AS4 PassDesc *pd) {
-  return TableSrc{(const AS4 uint64_t *)pd->in_tab, (const AS4 uint64_t *)pd->out_tab,
-                  (const AS4 uint32_t *)pd->lift_tab, (int)pd->k, pd->S, pd->pitch, (int)pd->nout};
+  const PassDesc d = *pd;
+  return table_src(d);
 }
 
 template <int RING>
@@ -93,13 +110,23 @@ __device__ __forceinline__ void run_tile(const AS4 PassDesc *pd, uint32_t col0, 
   dev::code_tile<R.w, R.n, R.p, kMaxOut, kBatchV[RING]>(table_src(pd), col0, col1, lane);
 }
 
-template <int RING>
-__device__ __forceinline__ void run_chunk(const AS4 PassDesc *pd, uint32_t base, uint32_t lane) {
+// LDS exchange of the split-K grid kernel, in dwords: kMaxOut outputs x the
+// largest w * V over the rings x 64 lanes.
+constexpr int xch_dwords() {
+  int m = 0;
+  for (int i = 0; i < kNumRings; ++i) m = kRings[i].w * kBatchV[i] > m ? kRings[i].w * kBatchV[i] : m;
+  return kMaxOut * m * 64;
+}
+
+template <int RING, int KS>
+__device__ __forceinline__ void run_chunk(const PassDesc &pd, uint32_t base, uint32_t lane,
+                                          uint32_t part, uint32_t *xch) {
   constexpr RingDesc R = kRings[RING];
   constexpr int V = kBatchV[RING];
+  typedef typename dev::Vec<V>::T T;
   const TableSrc src = table_src(pd);
   const uint32_t col = base + lane * 4u * V;
-  dev::code_column<R.w, R.n, R.p, kMaxOut, V>(src, col, col < src.S());
+  dev::code_column<R.w, R.n, R.p, kMaxOut, V, KS>(src, col, col < src.S(), part, (T *)xch);
 }
 
 __device__ __forceinline__ void code_item(const AS4 PassDesc *passes, const AS4 WorkItem *it,
@@ -124,8 +151,13 @@ __device__ __forceinline__ void code_item(const AS4 PassDesc *passes, const AS4 
 // The dispatcher deals workgroups round-robin over the XCDs (workgroup i to
 // XCD i mod 8).  With XCD_ORDER the workgroup-to-item map is permuted so that
 // each XCD walks its own contiguous eighth of the queue.
-template <int WG, bool XCD_ORDER>
+//
+// KS = 2 (split-K, 128-thread workgroups only): the two waves share one
+// chunk, each coding every other input block (see code_column).
+template <int WG, bool XCD_ORDER, int KS>
 __global__ __launch_bounds__(WG) void batch_grid_kernel(const BatchArgs a) {
+  static_assert(KS == 1 || WG == 64 * KS, "split-K workgroups hold one chunk");
+  __shared__ __attribute__((aligned(16))) uint32_t xch[KS > 1 ? xch_dwords() : 1];
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const AS4 uint32_t *starts = (const AS4 uint32_t *)a.starts;
@@ -141,17 +173,24 @@ __global__ __launch_bounds__(WG) void batch_grid_kernel(const BatchArgs a) {
     if (starts[mid] <= b) lo = mid;
     else hi = mid;
   }
-  const AS4 PassDesc *pd = (const AS4 PassDesc *)a.passes + lo;
-  const uint32_t ring = pd->ring;
+  // the whole descriptor and the pass's first item index in one round of
+  // scalar loads
+  const PassDesc pd = ((const AS4 PassDesc *)a.passes)[lo];
+  const uint32_t first = starts[lo];
+  const uint32_t ring = pd.ring;
   const uint32_t chunk = chunk_bytes(ring);
-  const uint32_t base = ((b - starts[lo]) * (WG / 64) + wave) * chunk;
-  if (base >= pd->S) return;
+  const uint32_t base = ((b - first) * (WG / 64 / KS) + wave / KS) * chunk;
+  const uint32_t part = wave % KS;
+  // a workgroup of one chunk never starts past the end of its pass; with
+  // several, both waves of a split-K pair leave together
+  if constexpr (WG / 64 / KS > 1)
+    if (base >= pd.S) return;
   switch (ring) {
-    case 0: run_chunk<0>(pd, base, lane); break;
-    case 1: run_chunk<1>(pd, base, lane); break;
-    case 2: run_chunk<2>(pd, base, lane); break;
-    case 3: run_chunk<3>(pd, base, lane); break;
-    case 4: run_chunk<4>(pd, base, lane); break;
+    case 0: run_chunk<0, KS>(pd, base, lane, part, xch); break;
+    case 1: run_chunk<1, KS>(pd, base, lane, part, xch); break;
+    case 2: run_chunk<2, KS>(pd, base, lane, part, xch); break;
+    case 3: run_chunk<3, KS>(pd, base, lane, part, xch); break;
+    case 4: run_chunk<4, KS>(pd, base, lane, part, xch); break;
     default: break;
   }
 }
@@ -200,11 +239,15 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(5))) void ba
   }
 }
 
-static const void *grid_fn(int wg, bool xcd) {
+static const void *grid_fn(int wg, bool xcd, int split) {
+  if (split == 2)
+    return wg == 128 ? (xcd ? (const void *)batch_grid_kernel<128, true, 2>
+                            : (const void *)batch_grid_kernel<128, false, 2>)
+                     : nullptr;
   switch (wg) {
-    case 64: return xcd ? (const void *)batch_grid_kernel<64, true> : (const void *)batch_grid_kernel<64, false>;
-    case 128: return xcd ? (const void *)batch_grid_kernel<128, true> : (const void *)batch_grid_kernel<128, false>;
-    case 256: return xcd ? (const void *)batch_grid_kernel<256, true> : (const void *)batch_grid_kernel<256, false>;
+    case 64: return xcd ? (const void *)batch_grid_kernel<64, true, 1> : (const void *)batch_grid_kernel<64, false, 1>;
+    case 128: return xcd ? (const void *)batch_grid_kernel<128, true, 1> : (const void *)batch_grid_kernel<128, false, 1>;
+    case 256: return xcd ? (const void *)batch_grid_kernel<256, true, 1> : (const void *)batch_grid_kernel<256, false, 1>;
     default: return nullptr;
   }
 }
@@ -298,8 +341,8 @@ uint64_t item_cost(const HostPass &hp, const WorkItem &wi) {
   return (uint64_t)(hp.k + hp.nout) * hp.w * (wi.col1 - wi.col0) + (uint64_t)hp.k * hp.w * 1024u;
 }
 
-const void *kernel_fn(int mode, int wg, int xcd_order) {
-  return mode == kModeGrid ? grid_fn(wg, xcd_order != 0) : persistent_fn(wg, mode);
+const void *kernel_fn(int mode, int wg, int xcd_order, int split) {
+  return mode == kModeGrid ? grid_fn(wg, xcd_order != 0, split) : persistent_fn(wg, mode);
 }
 
 }  // namespace
@@ -311,6 +354,9 @@ int batch_check_tune(pyrit_tune *t) {
   if (t->xcd_order != 0 && t->xcd_order != 1) return PYRIT_EINVAL;
   if (t->wg_threads == 0) t->wg_threads = 128;
   if (t->wg_threads != 64 && t->wg_threads != 128 && t->wg_threads != 256) return PYRIT_EINVAL;
+  if (t->split_k < 0 || t->split_k > 2) return PYRIT_EINVAL;
+  if (t->split_k == 0) t->split_k = (t->mode == kModeGrid && t->wg_threads == 128) ? 2 : 1;
+  if (t->split_k == 2 && (t->mode != kModeGrid || t->wg_threads != 128)) return PYRIT_EINVAL;
   return PYRIT_OK;
 }
 
@@ -319,7 +365,7 @@ int batch_resident_grid(const pyrit_tune &t, int *grid) {
   if (hipGetDevice(&dev) != hipSuccess) return PYRIT_EHIP;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return PYRIT_EHIP;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel_fn(t.mode, t.wg_threads, 0),
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel_fn(t.mode, t.wg_threads, 0, 1),
                                                    t.wg_threads, 0) != hipSuccess)
     return PYRIT_EHIP;
   int g = t.grid ? t.grid : std::max(1, per_cu * ncu);
@@ -357,7 +403,7 @@ int build_batch_image(const pyrit_batch_item *items, int n_items, const pyrit_tu
     const uint32_t chunk = chunk_bytes(hp.ring);
     uint64_t T;
     if (!persistent) {
-      T = (uint64_t)chunk * wpw;
+      T = (uint64_t)chunk * (wpw / (uint32_t)t.split_k);
     } else {
       T = t.tile_bytes ? (uint64_t)t.tile_bytes : cols / ((uint64_t)total_waves * 4 + 1);
       T = align_up(std::max<uint64_t>(chunk, std::min<uint64_t>(T, 65536)), chunk);
@@ -456,6 +502,7 @@ int build_batch_image(const pyrit_batch_item *items, int n_items, const pyrit_tu
   bi->mode = t.mode;
   bi->wg = t.wg_threads;
   bi->xcd_order = t.xcd_order;
+  bi->split = t.split_k;
   bi->grid = persistent ? grid : (int)work.size();
   return PYRIT_OK;
 }
@@ -476,7 +523,7 @@ int launch_batch_image(const BatchImage &bi, void *dev, void *stream) {
   if (bi.n_items == 0) return PYRIT_OK;
   BatchArgs a = image_args(bi, dev);
   void *kargs[] = {&a};
-  return hipLaunchKernel(kernel_fn(bi.mode, bi.wg, bi.xcd_order), dim3(bi.grid), dim3(bi.wg), kargs, 0,
+  return hipLaunchKernel(kernel_fn(bi.mode, bi.wg, bi.xcd_order, bi.split), dim3(bi.grid), dim3(bi.wg), kargs, 0,
                          (hipStream_t)stream) == hipSuccess
              ? PYRIT_OK
              : PYRIT_EHIP;
@@ -534,7 +581,7 @@ int pyrit_batch_create(const pyrit_batch_item *items, int n_items, const pyrit_t
   if (hipGraphCreate(&b->graph, 0) != hipSuccess) return PYRIT_EHIP;
   hipKernelNodeParams kp{};
   void *kargs[] = {&b->args};
-  kp.func = const_cast<void *>(kernel_fn(b->bi.mode, b->bi.wg, b->bi.xcd_order));
+  kp.func = const_cast<void *>(kernel_fn(b->bi.mode, b->bi.wg, b->bi.xcd_order, b->bi.split));
   kp.gridDim = dim3(b->bi.grid);
   kp.blockDim = dim3(b->bi.wg);
   kp.sharedMemBytes = 0;

@@ -86,7 +86,7 @@ struct BatchImage {
   std::vector<uint8_t> img;
   size_t off_start = 0, off_pass = 0, off_item = 0;
   uint32_t n_items = 0, n_passes = 0, total_waves = 0;
-  int grid = 0, wg = 128, mode = 0, xcd_order = 0;
+  int grid = 0, wg = 128, mode = 0, xcd_order = 0, split = 1;
   uint64_t moved = 0;
 };
 int batch_check_tune(pyrit_tune *t);

@@ -1,23 +1,28 @@
 // Plain per-stripe kernel: one launch codes one pass (up to kMaxOut outputs)
-// of one stripe; lane i of workgroup b owns column (b*kPlainWG + i) * 4V.
+// of one stripe.  Workgroup b is two waves sharing the column chunk of 64
+// lanes x 4V bytes at b * 256V (split-K: each wave codes every other input
+// block; partial sums meet in LDS).
 #pragma once
 #include "ring_kernels.hpp"
 
 namespace pyrit {
 
-// Two waves per workgroup: measured as fast as or faster than 256 threads.
 constexpr uint32_t kPlainWG = 128;
 
 template <int RING, int MO, int V>
 __global__ __launch_bounds__(kPlainWG) void plain_pass_kernel(const PassArgs a) {
   constexpr RingDesc R = kRings[RING];
-  const uint32_t col = (blockIdx.x * kPlainWG + threadIdx.x) * (4u * V);
-  dev::code_column<R.w, R.n, R.p, MO, V>(dev::KernargSrc{a}, col, col < a.S);
+  typedef typename dev::Vec<V>::T T;
+  __shared__ T xch[MO * R.w * 64];
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t part = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t col = (blockIdx.x * 64u + lane) * (4u * V);
+  dev::code_column<R.w, R.n, R.p, MO, V, 2>(dev::KernargSrc{a}, col, col < a.S, part, xch);
 }
 
 template <int RING, int MO, int V>
 static int launch_plain(const PassArgs &a, hipStream_t st) {
-  const uint32_t per_block = kPlainWG * 4u * V;
+  const uint32_t per_block = 64u * 4u * V;
   const uint32_t blocks = (a.S + per_block - 1) / per_block;
   hipLaunchKernelGGL((plain_pass_kernel<RING, MO, V>), dim3(blocks), dim3(kPlainWG), 0, st, a);
   return hipGetLastError() == hipSuccess ? PYRIT_OK : PYRIT_EHIP;

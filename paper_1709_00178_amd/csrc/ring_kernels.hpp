@@ -115,11 +115,25 @@ __device__ __forceinline__ void load_block(typename Vec<V>::T (&d)[W], const uin
 }
 
 // One lane column of one pass.  Src supplies wave-uniform values:
-//   k(), S(), pitch(), nout(), in(j), out(r), lift(j, r); slice t of a block
+//   k(), S(), pitch(), nout(), in(j), out(r), lift(j, r) and lift4(j) (the
+//   kMaxOut lifted coefficients of input j in one load); slice t of a block
 //   starts t * pitch() bytes after its base.  Rows r >= nout() must have
 //   zero lifted coefficients; they are neither reduced nor stored.
-template <int W, int N, uint32_t P, int MO, int V, class Src>
-__device__ __forceinline__ void code_column(const Src &src, uint32_t col, bool live) {
+//
+// KS = 1: the wave codes every input block of its column chunk.
+// KS = 2 (split-K): the two waves of a 128-thread workgroup share one column
+// chunk.  Wave `part` codes input blocks part, part + 2, ...; each reduces
+// its partial sums mod p (reduction is linear), wave part keeps outputs
+// r = part, part + 2, ... and hands the other outputs' partial slices to the
+// other wave through LDS (`xch`: MO x W x 64 lane values, one writer each).
+// Half as many columns are in flight for the same number of waves, which
+// shrinks the set of HBM rows open at once (measured on MI355X: 6.6 -> 7.0
+// TB/s for the 10-in/4-out, 8-slice access pattern).
+template <int W, int N, uint32_t P, int MO, int V, int KS = 1, class Src>
+__device__ __forceinline__ void code_column(const Src &src, uint32_t col, bool live,
+                                            uint32_t part = 0,
+                                            typename Vec<V>::T *xch = nullptr) {
+  static_assert(KS == 1 || KS == 2, "split factor");
   typedef typename Vec<V>::T T;
   const int k = src.k();
   const uint32_t S = src.S();
@@ -131,33 +145,66 @@ __device__ __forceinline__ void code_column(const Src &src, uint32_t col, bool l
 #pragma unroll
     for (int i = 0; i < N; ++i) acc[r][i] = (T)0;
 
-  // Two register sets: block j+1 is in flight while block j is accumulated.
-  // The prefetch after the last block uses an empty descriptor.  (Deeper
-  // register prefetch measured no faster on MI355X: it costs occupancy.)
+  // Two register sets: the wave's next block is in flight while the current
+  // one is accumulated.  The prefetch after the last block uses an empty
+  // descriptor.  (Deeper register prefetch measured no faster on MI355X: it
+  // costs occupancy.)
   T d[2][W];
-  auto prefetch = [&](int slot, int jj) {
-    const bool ok = jj < k;
-    load_block<W, V>(d[slot], src.in(ok ? jj : k - 1), ok ? span : 0u, pitch, col);
+  auto clampj = [&](int jj) { return jj < k ? jj : k - 1; };
+  auto prefetch = [&](int slot, int jj, const uint8_t *base) {
+    load_block<W, V>(d[slot], base, jj < k ? span : 0u, pitch, col);
   };
-  prefetch(0, 0);
-  for (int j = 0; j < k; j += 2) {
+  // Scalar operands run ahead of their use: the block pointer one prefetch
+  // ahead and the lifted coefficients one block ahead (one 16-byte scalar
+  // load), so no scalar-load wait sits between the vector loads and XORs.
+  prefetch(0, (int)part, src.in(clampj((int)part)));
+  const uint8_t *ip = src.in(clampj((int)part + KS));
+  u32x4 cf = src.lift4(clampj((int)part));
+  for (int j = (int)part; j < k; j += 2 * KS) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-      if (j + q >= k) break;
-      prefetch(q ^ 1, j + q + 1);
+      const int jq = j + q * KS;
+      if (jq >= k) break;
+      prefetch(q ^ 1, jq + KS, ip);
+      ip = src.in(clampj(jq + 2 * KS));
+      const u32x4 cn = src.lift4(clampj(jq + KS));
 #pragma unroll
-      for (int r = 0; r < MO; ++r) rot_acc<W, N, 0, T>(acc[r], d[q], src.lift(j + q, r));
+      for (int r = 0; r < MO; ++r) rot_acc<W, N, 0, T>(acc[r], d[q], cf[r]);
+      cf = cn;
     }
   }
 
-  if (!live) return;
+  if constexpr (KS == 1) {
+    if (!live) return;
 #pragma unroll
-  for (int r = 0; r < MO; ++r) {
-    if (r >= src.nout()) break;
-    reduce_mod_p<W, N, P, T>(acc[r]);
-    const __amdgpu_buffer_rsrc_t o = block_rsrc(src.out(r), span);
+    for (int r = 0; r < MO; ++r) {
+      if (r >= src.nout()) break;
+      reduce_mod_p<W, N, P, T>(acc[r]);
+      const __amdgpu_buffer_rsrc_t o = block_rsrc(src.out(r), span);
 #pragma unroll
-    for (int t = 0; t < W; ++t) bstore<V>(acc[r][t], o, col, t * pitch);
+      for (int t = 0; t < W; ++t) bstore<V>(acc[r][t], o, col, t * pitch);
+    }
+  } else {
+    const uint32_t lane = __lane_id();
+#pragma unroll
+    for (int r = 0; r < MO; ++r) {
+      if (r >= src.nout()) break;
+      reduce_mod_p<W, N, P, T>(acc[r]);
+      if ((uint32_t)(r & 1) != part) {
+#pragma unroll
+        for (int t = 0; t < W; ++t) xch[(r * W + t) * 64 + lane] = acc[r][t];
+      }
+    }
+    __syncthreads();
+    if (!live) return;
+#pragma unroll
+    for (int r = 0; r < MO; ++r) {
+      if (r >= src.nout()) break;
+      if ((uint32_t)(r & 1) != part) continue;
+      const __amdgpu_buffer_rsrc_t o = block_rsrc(src.out(r), span);
+#pragma unroll
+      for (int t = 0; t < W; ++t) bstore<V>(acc[r][t] ^ xch[(r * W + t) * 64 + lane], o, col, t * pitch);
+    }
   }
 }
 
@@ -234,6 +281,7 @@ struct KernargSrc {
   __device__ const uint8_t *in(int j) const { return a.in[j]; }
   __device__ uint8_t *out(int r) const { return a.out[r]; }
   __device__ uint32_t lift(int j, int r) const { return a.lift[j][r]; }
+  __device__ u32x4 lift4(int j) const { return *(const u32x4 *)&a.lift[j][0]; }
 };
 
 }  // namespace dev

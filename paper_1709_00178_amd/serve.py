@@ -46,10 +46,10 @@ class Server:
                  per_request: bool = False, release_outputs: bool = True,
                  block_skew: int = 4352, mode: str = "grid", wg_threads: int = 0,
                  tile_bytes: int = 0, slot_bytes: int = 0, large_bytes: int = 64 << 20,
-                 xcd_order: int = 0):
+                 xcd_order: int = 0, split_k: int = 0):
         cfg = ServeConfig(pool_bytes, slots, max_batch, 1 if per_request else 0,
                           1 if release_outputs else 0, block_skew, slot_bytes, large_bytes,
-                          Tune(BATCH_MODES[mode], tile_bytes, 0, wg_threads, xcd_order))
+                          Tune(BATCH_MODES[mode], tile_bytes, 0, wg_threads, xcd_order, split_k))
         h = ctypes.c_void_p()
         _check(lib().pyrit_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h

@@ -74,18 +74,22 @@ def test_batch_single_stripe_every_shape():
     bufs, items = _build([st], plans, arena)
     host = W.host_blocks(st)
     want = oracle.Field(st.w, st.p).encode(plans.get(st).G, host, st.S, nthreads=4)
-    shapes = [("grid", 0, 0), ("grid", 0, 1), ("queue", 0, 0), ("queue", 512, 0),
-              ("queue", 4096, 0), ("static", 0, 0), ("static", 512, 0), ("static", 4096, 0)]
+    shapes = [("grid", 0, 0, 1), ("grid", 0, 1, 1), ("grid", 0, 0, 2), ("grid", 0, 1, 2),
+              ("queue", 0, 0, 1), ("queue", 512, 0, 1), ("queue", 4096, 0, 1), ("static", 0, 0, 1),
+              ("static", 512, 0, 1), ("static", 4096, 0, 1)]
     for wg in [64, 128, 256]:
-        for mode, tile, xcd in shapes:
-            b = P.Batch(items, mode=mode, tile_bytes=tile, wg_threads=wg, xcd_order=xcd)
+        for mode, tile, xcd, split in shapes:
+            if split == 2 and wg != 128:
+                continue
+            b = P.Batch(items, mode=mode, tile_bytes=tile, wg_threads=wg, xcd_order=xcd,
+                        split_k=split)
             for launch in [b.launch, b.launch_direct, b.launch, b.run]:
                 _clear_outputs(bufs, 0xEE)
                 launch()
                 sync()
                 for i in range(st.m):
                     got = to_host(bufs[0][0][st.k + i])
-                    assert np.array_equal(got, want[i]), (wg, mode, tile, xcd, i)
+                    assert np.array_equal(got, want[i]), (wg, mode, tile, xcd, split, i)
             b.close()
 
 
@@ -105,13 +109,14 @@ def test_batch_graph_replays_with_eager_work_between(mode):
         _check_stripes(stripes, bufs, plans, ncols=8, seed=rep)
 
 
-@pytest.mark.parametrize("mode,xcd", [("grid", 0), ("grid", 1), ("queue", 0), ("static", 0)])
-def test_c2_all_stripes_one_launch(mode, xcd):
+@pytest.mark.parametrize("mode,xcd,split", [("grid", 0, 1), ("grid", 1, 1), ("grid", 1, 2),
+                                            ("queue", 0, 1), ("static", 0, 1)])
+def test_c2_all_stripes_one_launch(mode, xcd, split):
     stripes = W.c2()
     plans = PlanCache()
     arena = Arena(sum(stripe_bytes_needed(s) for s in stripes) + 4096)
     bufs, items = _build(stripes, plans, arena)
-    b = P.Batch(items, mode=mode, xcd_order=xcd)
+    b = P.Batch(items, mode=mode, xcd_order=xcd, split_k=split)
     info = b.info()
     assert info["passes"] == 256
     assert info["moved_bytes"] == sum(s.moved_bytes() for s in stripes)
@@ -120,21 +125,40 @@ def test_c2_all_stripes_one_launch(mode, xcd):
     _check_stripes(stripes, bufs, plans, ncols=12)
 
 
-@pytest.mark.parametrize("mode,xcd", [("grid", 0), ("grid", 1), ("queue", 0), ("static", 0)])
-def test_c3_all_4096_uneven_stripes_one_launch(mode, xcd):
+@pytest.mark.parametrize("mode,xcd,split", [("grid", 0, 1), ("grid", 1, 1), ("grid", 0, 2),
+                                            ("grid", 1, 2), ("queue", 0, 1), ("static", 0, 1)])
+def test_c3_all_4096_uneven_stripes_one_launch(mode, xcd, split):
     """The uneven batch: w in {4,8,10}, k in [4,16], m in [2,4], 4 KiB..4 MiB
     blocks, 30% decodes, all in one launch."""
     stripes = W.c3()
     plans = PlanCache()
     arena = Arena(sum(stripe_bytes_needed(s) for s in stripes) + 4096)
     bufs, items = _build(stripes, plans, arena)
-    b = P.Batch(items, mode=mode, xcd_order=xcd)
+    b = P.Batch(items, mode=mode, xcd_order=xcd, split_k=split)
     info = b.info()
     assert info["moved_bytes"] == sum(s.moved_bytes() for s in stripes)
     _clear_outputs(bufs, 0x77)
     b.launch()
     sync()
     _check_stripes(stripes, bufs, plans, ncols=10)
+
+
+def test_c1_code_64_stripes_one_launch():
+    """The headline code over 64 stripes of 1 MiB blocks in one launch (the
+    bench's many-stripe leg), every stripe against the oracle."""
+    base = W.c1()
+    stripes = [W.Stripe(base.w, base.n, base.p, k=base.k, m=base.m, B=1 << 20, stripe=i,
+                        seed=base.seed) for i in range(64)]
+    plans = PlanCache()
+    arena = Arena(sum(stripe_bytes_needed(s) for s in stripes) + 4096)
+    bufs, items = _build(stripes, plans, arena)
+    for cfg in [dict(split_k=2), dict(split_k=2, xcd_order=1), dict(wg_threads=256, split_k=1)]:
+        _clear_outputs(bufs, 0x5A)
+        b = P.Batch(items, mode="grid", **cfg)
+        b.run()
+        sync()
+        _check_stripes(stripes, bufs, plans, ncols=8)
+        b.close()
 
 
 def test_batch_matches_plain_kernel_bytes():
@@ -150,14 +174,14 @@ def test_batch_matches_plain_kernel_bytes():
     par_plain = [arena.take(st.block_len) for _ in range(st.m)]
     par_batch = [arena.take(st.block_len) for _ in range(st.m)]
     plan.encode(data, par_plain, st.S)
-    for mode in ["grid", "queue", "static"]:
+    for mode, split in [("grid", 1), ("grid", 2), ("queue", 1), ("static", 1)]:
         for t in par_batch:
             t.zero_()
-        b = P.Batch([(plan, [], data + par_batch, st.S)], mode=mode)
+        b = P.Batch([(plan, [], data + par_batch, st.S)], mode=mode, split_k=split)
         b.launch()
         sync()
         for a, c in zip(par_plain, par_batch):
-            assert torch.equal(a, c), mode
+            assert torch.equal(a, c), (mode, split)
     # decode two data blocks and two parity blocks through the batch path
     er = [1, 7, 11, 14]
     blocks = data + par_plain
@@ -191,6 +215,11 @@ def test_batch_errors():
     with pytest.raises(P.PyritError) as e:
         P.Batch([(plan, [], blocks, st.S)], xcd_order=2)
     assert e.value.code == -1
+    for bad_split in [dict(split_k=3), dict(split_k=2, wg_threads=256),
+                      dict(split_k=2, mode="queue", wg_threads=128)]:
+        with pytest.raises(P.PyritError) as e:
+            P.Batch([(plan, [], blocks, st.S)], **bad_split)
+        assert e.value.code == -1, bad_split
     with pytest.raises(ValueError):
         P.Batch([(plan, [], blocks, st.S)], mode="fifo")
     with pytest.raises(ValueError):
