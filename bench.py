@@ -4,7 +4,7 @@ same kernel, both timed, the faster runs the steps), beside the plain
 per-stripe kernel, decode, the 256-stripe and 4096-stripe batches, the
 HBM roofline and the CPU oracle.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--only c1,c2,c3]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--only c1,c1s,c2,c3,c4]
 
 Prints ONE JSON line.  A step is one encode of the whole stripe (10 data
 blocks of 64 MiB, 4 parity blocks of 64 MiB), inputs already resident in HBM.
@@ -437,7 +437,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", default="c1,c2,c3,c4", help="comma list of c1,c2,c3,c4")
+    ap.add_argument("--only", default="c1,c1s,c2,c3,c4",
+                    help="comma list of c1 (headline stripe), c1s (64 stripes of the same "
+                         "code), c2, c3, c4")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported. Stripes (or "
@@ -470,6 +472,7 @@ def main():
 
     if "c1" in only:
         bench_c1(args, stream, out, log)
+    if "c1s" in only:
         bench_c1_stripes(args, stream, out, log)
     if "c2" in only:
         bench_c2(args, stream, out, log)
