@@ -98,9 +98,24 @@ __device__ __forceinline__ TableSrc table_src(const PassDesc &d) {
                   (const AS4 uint32_t *)d.lift_tab, (int)d.k, d.S, d.pitch, (int)d.nout};
 }
 
+// A register copy of a descriptor (field by field: a constant-address-space
+// object has no implicit copy into a generic one).
+__device__ __forceinline__ PassDesc load_desc(const AS4 PassDesc *p) {
+  PassDesc d;
+  d.in_tab = p->in_tab;
+  d.out_tab = p->out_tab;
+  d.lift_tab = p->lift_tab;
+  d.k = p->k;
+  d.nout = p->nout;
+  d.S = p->S;
+  d.ring = p->ring;
+  d.pitch = p->pitch;
+  d.pad = p->pad;
+  return d;
+}
+
 __device__ __forceinline__ TableSrc table_src(const AS4 PassDesc *pd) {
-  const PassDesc d = *pd;
-  return table_src(d);
+  return table_src(load_desc(pd));
 }
 
 template <int RING>
@@ -175,7 +190,7 @@ __global__ __launch_bounds__(WG) void batch_grid_kernel(const BatchArgs a) {
   }
   // the whole descriptor and the pass's first item index in one round of
   // scalar loads
-  const PassDesc pd = ((const AS4 PassDesc *)a.passes)[lo];
+  const PassDesc pd = load_desc((const AS4 PassDesc *)a.passes + lo);
   const uint32_t first = starts[lo];
   const uint32_t ring = pd.ring;
   const uint32_t chunk = chunk_bytes(ring);
