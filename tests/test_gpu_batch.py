@@ -161,6 +161,27 @@ def test_c1_code_64_stripes_one_launch():
         b.close()
 
 
+@pytest.mark.parametrize("split", [1, 2])
+def test_every_ring_in_one_batch(split):
+    """All five rings (both degree-8 factors of x^17+1 and the ESP ring
+    x^6+x^3+1 included), encodes and decodes, uneven sizes, one launch."""
+    rings = [(4, 5, 0x1F), (8, 17, 0x139), (8, 17, 0x1D7), (10, 11, 0x7FF), (6, 9, 0x49)]
+    stripes = []
+    for i, (w, n, p) in enumerate(rings * 3):
+        k, m = (4 + i % 7, 2 + i % 3) if w != 4 else (4 + i % 5, 2 + i % 3)
+        erased = () if i % 3 == 0 else tuple(sorted({(i * 5) % (k + m), (i * 7 + 1) % (k + m)}))[:m]
+        B = (37 + 91 * i) * 64 * w
+        stripes.append(W.Stripe(w, n, p, k=k, m=m, B=B, erased=erased, stripe=i, seed=99))
+    plans = PlanCache()
+    arena = Arena(sum(stripe_bytes_needed(s) for s in stripes) + 4096)
+    bufs, items = _build(stripes, plans, arena)
+    _clear_outputs(bufs, 0x3C)
+    b = P.Batch(items, mode="grid", wg_threads=128, split_k=split)
+    b.run()
+    sync()
+    _check_stripes(stripes, bufs, plans, ncols=16)
+
+
 def test_batch_matches_plain_kernel_bytes():
     """Batched and plain outputs are identical for C1-shaped stripes with
     6 outputs (two passes) and a decode."""
