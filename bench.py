@@ -280,6 +280,23 @@ def bench_c1(args, stream, out, log):
     P.copy(dst, src, stream=stream)
     cp_ms = batch_time_ms(lambda: P.copy(dst, src, stream=stream), 20, stream)
     out["copy_ceiling_GBps"] = round(2 * half / (cp_ms * 1e-3) / 1e9, 1)
+    # the C1 stripe under the generalized Cauchy matrix of small lifted weight
+    G, _, _, wl = P.cauchy_light(st.w, st.n, st.p, st.k, st.m)
+    lplan = P.Plan(st.w, st.n, st.p, st.k, st.m, G=G)
+    lbatch = P.Batch([(lplan, [], blocks, st.S, st.pitch)], **res["batched"]["executor"])
+
+    def enc_light_plain():
+        lplan.encode(blocks[:st.k], blocks[st.k:], st.S, stream=stream, pitch=st.pitch)
+
+    for _ in range(3):
+        enc_light_plain()
+        lbatch.run(stream)
+    lp_ms = min(batch_time_ms(enc_light_plain, 20, stream) for _ in range(3))
+    lb_ms = min(batch_time_ms(lambda: lbatch.run(stream), 20, stream) for _ in range(3))
+    out["c1"]["light_cauchy"] = {"weight": wl, "plain_cauchy_weight": plan.weight,
+                                 "plain_GBps_moved": round(moved / (lp_ms * 1e-3) / 1e9, 1),
+                                 "batched_GBps_moved": round(moved / (lb_ms * 1e-3) / 1e9, 1)}
+    del lbatch
     del batch, dbatch, arena, blocks
     torch.cuda.empty_cache()
 
@@ -361,7 +378,18 @@ def bench_c2(args, stream, out, log):
                                       "frac_of_peak": round(moved / (b_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
                                       "executor": cfg,
                                       "work_items": batch.info()["work_items"]}}
-    del batch, arena, bl
+    # the same stripes under the generalized Cauchy matrix of small lifted
+    # weight (different parity bytes: a different code of the same shape)
+    G, _, _, wl = P.cauchy_light(st0.w, st0.n, st0.p, st0.k, st0.m)
+    lplan = P.Plan(st0.w, st0.n, st0.p, st0.k, st0.m, G=G)
+    lbatch = P.Batch([(lplan, [], b, st.S) for st, b in zip(stripes, bl)], **cfg)
+    lbatch.run(stream)
+    l_ms = batch_time_ms(lambda: lbatch.run(stream), 10, stream)
+    out["c2"]["light_cauchy"] = {"weight": wl, "plain_cauchy_weight": plan.weight,
+                                 "batched_ms": round(l_ms, 3),
+                                 "GBps_data": round(user / (l_ms * 1e-3) / 1e9, 1),
+                                 "frac_of_peak": round(moved / (l_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
+    del batch, lbatch, arena, bl
     torch.cuda.empty_cache()
 
 

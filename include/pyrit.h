@@ -101,6 +101,19 @@ int pyrit_gf_mul(int w, uint32_t p, uint32_t a, uint32_t b, uint32_t *c);
  * k + m <= 2^w.  G is a host array of m*k entries. */
 int pyrit_cauchy(int w, uint32_t p, int k, int m, uint16_t *G);
 
+/* Generalized Cauchy parity matrix of small ring weight (Sec. III codes with
+ * generalized Cauchy matrices; Sec. II-B: the XOR count is the number of
+ * ones of the lifted matrix):
+ *   G[i*k + j] = row_scale[i] * C[i][j] * col_scale[j],  C = pyrit_cauchy,
+ * with nonzero multipliers chosen by coordinate descent to lower the total
+ * weight of the lifted matrix in R_{2,n}.  Scaling rows and columns by
+ * nonzero elements keeps every square submatrix nonsingular, so G is MDS.
+ * row_scale (m entries), col_scale (k entries) and weight (the total lifted
+ * weight) may be NULL.  Deterministic.  Errors as pyrit_ring_check and
+ * pyrit_cauchy. */
+int pyrit_cauchy_light(int w, int n, uint32_t p, int k, int m, uint16_t *G, uint16_t *row_scale,
+                       uint16_t *col_scale, int *weight);
+
 /* -------------------------------------------------------------------- plans */
 typedef struct pyrit_plan pyrit_plan;
 

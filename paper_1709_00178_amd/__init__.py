@@ -75,6 +75,18 @@ def cauchy(w: int, p: int, k: int, m: int) -> np.ndarray:
     return G
 
 
+def cauchy_light(w: int, n: int, p: int, k: int, m: int):
+    """Generalized Cauchy matrix with row/column multipliers chosen for a
+    small lifted weight in R_{2,n}: returns (G, row_scale, col_scale, weight)."""
+    G = np.zeros((m, k), dtype=np.uint16)
+    rs = np.zeros(m, dtype=np.uint16)
+    cs = np.zeros(k, dtype=np.uint16)
+    wt = ctypes.c_int()
+    _check(lib().pyrit_cauchy_light(w, n, p, k, m, G.ctypes.data, rs.ctypes.data, cs.ctypes.data,
+                                    ctypes.byref(wt)))
+    return G, rs, cs, wt.value
+
+
 def _dev_ptr(x) -> int:
     if isinstance(x, int):
         return x

@@ -230,6 +230,63 @@ int pyrit_cauchy(int w, uint32_t p, int k, int m, uint16_t *G) {
   return PYRIT_OK;
 }
 
+int pyrit_cauchy_light(int w, int n, uint32_t p, int k, int m, uint16_t *G, uint16_t *row_scale,
+                       uint16_t *col_scale, int *weight) {
+  int rc = pyrit_ring_check(w, n, p);
+  if (rc) return rc;
+  rc = pyrit_cauchy(w, p, k, m, G);
+  if (rc) return rc;
+  const auto &lt = lift_table(w, n, p);
+  const uint32_t q = 1u << w;
+  std::vector<uint32_t> C((size_t)m * k), d(m, 1u), c(k, 1u);
+  for (size_t i = 0; i < C.size(); ++i) C[i] = G[i];
+  auto wt = [&](uint32_t u) { return __builtin_popcount(lt[u]); };
+  // Coordinate descent over the row and column multipliers: each step keeps
+  // the multiplier with the smallest total lifted weight of its row or
+  // column (ties: the smallest element), so the total never increases.
+  for (int round = 0; round < 16; ++round) {
+    bool changed = false;
+    for (int j = 0; j < k; ++j) {
+      uint32_t best = c[j];
+      long best_w = -1;
+      for (uint32_t a = 1; a < q; ++a) {
+        long s = 0;
+        for (int i = 0; i < m; ++i) s += wt(gf_mul(gf_mul(d[i], C[(size_t)i * k + j], p), a, p));
+        if (best_w < 0 || s < best_w) { best_w = s; best = a; }
+      }
+      long cur = 0;
+      for (int i = 0; i < m; ++i) cur += wt(gf_mul(gf_mul(d[i], C[(size_t)i * k + j], p), c[j], p));
+      if (best_w < cur) { c[j] = best; changed = true; }
+    }
+    for (int i = 0; i < m; ++i) {
+      uint32_t best = d[i];
+      long best_w = -1;
+      for (uint32_t a = 1; a < q; ++a) {
+        long s = 0;
+        for (int j = 0; j < k; ++j) s += wt(gf_mul(gf_mul(a, C[(size_t)i * k + j], p), c[j], p));
+        if (best_w < 0 || s < best_w) { best_w = s; best = a; }
+      }
+      long cur = 0;
+      for (int j = 0; j < k; ++j) cur += wt(gf_mul(gf_mul(d[i], C[(size_t)i * k + j], p), c[j], p));
+      if (best_w < cur) { d[i] = best; changed = true; }
+    }
+    if (!changed) break;
+  }
+  int total = 0;
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < k; ++j) {
+      const uint32_t g = gf_mul(gf_mul(d[i], C[(size_t)i * k + j], p), c[j], p);
+      G[(size_t)i * k + j] = (uint16_t)g;
+      total += wt(g);
+    }
+  if (row_scale)
+    for (int i = 0; i < m; ++i) row_scale[i] = (uint16_t)d[i];
+  if (col_scale)
+    for (int j = 0; j < k; ++j) col_scale[j] = (uint16_t)c[j];
+  if (weight) *weight = total;
+  return PYRIT_OK;
+}
+
 int pyrit_plan_create(int w, int n, uint32_t p, int k, int m, const uint16_t *G,
                       pyrit_plan **out) {
   if (!out || !G) return PYRIT_EINVAL;

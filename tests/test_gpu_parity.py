@@ -109,6 +109,29 @@ def test_many_outputs_and_shapes(w, n, p, k, m):
     _full_check(st, P.cauchy(w, p, k, m))
 
 
+@pytest.mark.parametrize("w,n,p,k,m", [(8, 17, 0x139, 10, 4), (10, 11, 0x7FF, 16, 4),
+                                       (6, 9, 0x49, 12, 4), (4, 5, 0x1F, 4, 2)])
+def test_light_cauchy_encode_and_decode(w, n, p, k, m):
+    """The generalized Cauchy matrix of small lifted weight: encode every byte
+    against the oracle with the same matrix, then decode a pattern with data
+    and parity erased."""
+    G = P.cauchy_light(w, n, p, k, m)[0]
+    st = W.Stripe(w, n, p, k=k, m=m, B=RAGGED_S * w, stripe=k + m, seed=11)
+    _full_check(st, G)
+    torch = torch_mod()
+    f = oracle.Field(w, p)
+    host = [W.block_bytes(st.key(j), st.block_len, st.B) for j in range(k)]
+    code = host + f.encode(G, host, st.S, nthreads=4)
+    dev = [torch.from_numpy(b).cuda() for b in code]
+    er = [0, k - 1, k + m - 1][:m]
+    for e in er:
+        dev[e].fill_(0x33)
+    P.Plan(w, n, p, k, m, G=G).decode(er, dev, st.S)
+    sync()
+    for e in er:
+        assert np.array_equal(to_host(dev[e]), code[e]), e
+
+
 @pytest.mark.parametrize("w,n,p", [(8, 17, 0x139), (10, 11, 0x7FF), (4, 5, 0x1F)])
 def test_minimum_slice_and_single_input(w, n, p):
     st = W.Stripe(w, n, p, k=1, m=3, B=64 * w, seed=6)

@@ -237,3 +237,68 @@ def test_decode_matrix_errors():
     with pytest.raises(P.PyritError) as e:
         sing.decode_matrix([0, 1])
     assert e.value.code == E["ESINGULAR"]
+
+
+# Generalized Cauchy of small ring weight.  Pins: the rank-1 scaling
+# structure against the oracle's multiply, nonsingular square submatrices by
+# schoolbook elimination, the weight against brute-force popcounts of the
+# lifted entries, and recovery from every pattern with the oracle's decoder.
+LIGHT = [((4, 5, 0x1F), 4, 2, 12), ((8, 17, 0x139), 10, 4, 72), ((10, 11, 0x7FF), 16, 4, 168),
+         ((8, 17, 0x1D7), 10, 4, 76), ((6, 9, 0x49), 12, 4, None)]
+
+
+@pytest.mark.parametrize("ring,k,m,want", LIGHT, ids=[f"{r[0]}-{r[1]}-{k}-{m}" for r, k, m, _ in LIGHT])
+def test_cauchy_light_structure_and_weight(ring, k, m, want):
+    w, n, p = ring
+    G, rs, cs, W_ = P.cauchy_light(w, n, p, k, m)
+    G2, rs2, cs2, W2 = P.cauchy_light(w, n, p, k, m)
+    assert np.array_equal(G, G2) and W_ == W2  # deterministic
+    f = oracle.Field(w, p)
+    C = f.cauchy(k, m)
+    assert (rs != 0).all() and (cs != 0).all()
+    for i in range(m):
+        for j in range(k):
+            assert int(G[i, j]) == f.mul(f.mul(int(rs[i]), int(C[i, j])), int(cs[j]))
+    lifted = [P.lift(w, n, p, int(g)) for g in G.ravel()]
+    assert W_ == sum(bin(c).count("1") for c in lifted)
+    assert W_ <= P.Plan(w, n, p, k, m).weight
+    if want is not None:
+        assert W_ == want
+    assert P.Plan(w, n, p, k, m, G=G).weight == W_
+
+
+@pytest.mark.parametrize("ring,k,m", [((4, 5, 0x1F), 4, 2), ((8, 17, 0x139), 10, 4)])
+def test_cauchy_light_is_mds(ring, k, m):
+    w, n, p = ring
+    G = P.cauchy_light(w, n, p, k, m)[0]
+    mats = []
+    for s in range(1, m + 1):
+        for rows in itertools.combinations(range(m), s):
+            for cols in itertools.combinations(range(k), s):
+                mats.append(G[np.ix_(rows, cols)])
+        ok = sb.det_nonzero_all(mats, w, p)
+        assert ok.all(), s
+        mats = []
+
+
+def test_cauchy_light_decodes_every_pattern_c0_and_c1():
+    for st, pats in [(W.c0(), [c for s in (1, 2) for c in itertools.combinations(range(6), s)]),
+                     (W.c1(), list(itertools.combinations(range(14), 4))[::7])]:
+        G = P.cauchy_light(st.w, st.n, st.p, st.k, st.m)[0]
+        f = oracle.Field(st.w, st.p)
+        rng = np.random.Generator(np.random.PCG64(5))
+        S = 64
+        data = [rng.integers(0, 256, st.w * S, dtype=np.uint8) for _ in range(st.k)]
+        code = data + f.encode(G, data, S)
+        plan = P.Plan(st.w, st.n, st.p, st.k, st.m, G=G)
+        for er in pats:
+            blocks = [c.copy() for c in code]
+            for e in er:
+                blocks[e][:] = 0
+            f.decode(G, list(er), blocks, S)
+            for e in er:
+                assert np.array_equal(blocks[e], code[e]), (st.w, er)
+            surv, D = plan.decode_matrix(list(er))
+            rec = sb.bitmatrix_encode(D, [code[s] for s in surv], st.w, st.p, S)
+            for e, blk in zip(er, rec):
+                assert np.array_equal(blk, code[e]), (st.w, er, e)
