@@ -4,7 +4,7 @@ same kernel, both timed, the faster runs the steps), beside the plain
 per-stripe kernel, decode, the 256-stripe and 4096-stripe batches, the
 HBM roofline and the CPU oracle.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--only c1,c1s,c2,c3,c4]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--only c1,c1s,layout,c2,c3,c4]
 
 Prints ONE JSON line.  A step is one encode of the whole stripe (10 data
 blocks of 64 MiB, 4 parity blocks of 64 MiB), inputs already resident in HBM.
@@ -343,6 +343,33 @@ def bench_c1_stripes(args, stream, out, log):
     torch.cuda.empty_cache()
 
 
+def bench_layout(args, stream, out, log):
+    """Symbol-major <-> bit-sliced conversion of one 64 MiB block (GF(2^8)
+    byte symbols and GF(2^10) 16-bit symbols)."""
+    import torch
+
+    import paper_1709_00178_amd as P
+    res = {}
+    for w, nsym in ((8, 64 << 20), (10, 32 << 20)):
+        sb = nsym * (1 if w <= 8 else 2)
+        sym = torch.empty(sb, dtype=torch.uint8, device="cuda")
+        P.fill_random(sym, 123)
+        sl = torch.empty(w * (nsym // 8), dtype=torch.uint8, device="cuda")
+        back = torch.empty_like(sym)
+        to = lambda: P.to_sliced(w, sym, sl, n_symbols=nsym, stream=stream)
+        fr = lambda: P.from_sliced(w, sl, back, n_symbols=nsym, stream=stream)
+        to(); fr()
+        t_ms = min(batch_time_ms(to, 20, stream) for _ in range(2))
+        f_ms = min(batch_time_ms(fr, 20, stream) for _ in range(2))
+        moved = sb + sl.numel()
+        res[f"w{w}"] = {"symbols": nsym, "to_sliced_GBps": round(moved / (t_ms * 1e-3) / 1e9, 1),
+                        "from_sliced_GBps": round(moved / (f_ms * 1e-3) / 1e9, 1),
+                        "to_ms": round(t_ms, 4), "from_ms": round(f_ms, 4)}
+        del sym, sl, back
+    out["layout_conversion"] = res
+    torch.cuda.empty_cache()
+
+
 def bench_c2(args, stream, out, log):
     import torch
 
@@ -465,9 +492,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", default="c1,c1s,c2,c3,c4",
+    ap.add_argument("--only", default="c1,c1s,layout,c2,c3,c4",
                     help="comma list of c1 (headline stripe), c1s (64 stripes of the same "
-                         "code), c2, c3, c4")
+                         "code), layout (symbol <-> bit-sliced conversion), c2, c3, c4")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported. Stripes (or "
@@ -502,6 +529,8 @@ def main():
         bench_c1(args, stream, out, log)
     if "c1s" in only:
         bench_c1_stripes(args, stream, out, log)
+    if "layout" in only:
+        bench_layout(args, stream, out, log)
     if "c2" in only:
         bench_c2(args, stream, out, log)
     if "c3" in only:

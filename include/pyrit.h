@@ -180,6 +180,24 @@ int pyrit_encode_ex(const pyrit_plan *plan, const uint8_t *const *data, uint8_t 
 int pyrit_decode_ex(const pyrit_plan *plan, const int *erased, int n_erased,
                     uint8_t *const *blocks, size_t slice_bytes, size_t slice_pitch, void *stream);
 
+/* ------------------------------------------------ symbol <-> bit-sliced layout
+ * The coding calls take bit-sliced blocks (a block as w chunks, Sec. III):
+ * slice t holds bit t of every symbol, symbol s at bit s mod 8 of byte s div 8
+ * of the slice.  These two calls convert a block of n_symbols ordinary
+ * symbols (one byte each for w <= 8, the low w bits; one little-endian 16-bit
+ * word each for 8 < w <= 16) to and from that layout on the device.
+ *   symbols: device pointer, n_symbols * (w <= 8 ? 1 : 2) bytes;
+ *   sliced:  device pointer, w slices of n_symbols / 8 bytes, slice t at
+ *            sliced + t * slice_pitch (0 = n_symbols / 8).
+ * n_symbols must be a positive multiple of 512 (whole 64-byte slice rows);
+ * both pointers 16-byte aligned; slice_pitch a multiple of 64.  Symbol bits at
+ * or above w are ignored on the way in and written as zero on the way out.
+ * Asynchronous on `stream`.  Errors: PYRIT_EINVAL, PYRIT_EALIGN, PYRIT_EHIP. */
+int pyrit_to_sliced(int w, const void *symbols, size_t n_symbols, uint8_t *sliced,
+                    size_t slice_pitch, void *stream);
+int pyrit_from_sliced(int w, const uint8_t *sliced, size_t slice_pitch, size_t n_symbols,
+                      void *symbols, void *stream);
+
 /* Fill nbytes of device memory with the seeded SplitMix64 stream (word q of
  * the buffer is mix64(key + (q+1) * 0x9E3779B97F4A7C15), little endian) for
  * bytes < nrandom, zero beyond.  nbytes must be a multiple of 8. */

@@ -170,3 +170,30 @@ class Field:
         _check(_lib.or_decode(self._h, k, m, C.ctypes.data, er, len(erased),
                               _ptr_array(blocks), S, o0, o1, nthreads))
         return blocks
+
+
+def to_sliced(w: int, symbols) -> np.ndarray:
+    """Bit-sliced block of ``symbols`` (n symbols, n a multiple of 8): slice t
+    holds bit t of every symbol, symbol 8o + b at bit b of byte o (the
+    block's w chunks, Sec. III).  Returns w * n/8 bytes, slice after slice."""
+    u = np.asarray(symbols).astype(np.uint32).reshape(-1)
+    n = u.size
+    assert n % 8 == 0
+    S = n // 8
+    out = np.zeros((w, S), dtype=np.uint32)
+    for t in range(w):
+        bits = ((u >> t) & 1).reshape(S, 8)
+        for b in range(8):
+            out[t] |= bits[:, b] << b
+    return out.astype(np.uint8).reshape(-1)
+
+
+def from_sliced(w: int, sliced, n: int) -> np.ndarray:
+    """Inverse of `to_sliced`: the n symbols (uint16) of a bit-sliced block."""
+    S = n // 8
+    blk = np.asarray(sliced, dtype=np.uint8).reshape(w, S).astype(np.uint32)
+    sym = np.zeros((S, 8), dtype=np.uint32)
+    for t in range(w):
+        for b in range(8):
+            sym[:, b] |= ((blk[t] >> b) & 1) << t
+    return sym.reshape(-1).astype(np.uint16)

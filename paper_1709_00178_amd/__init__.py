@@ -275,3 +275,22 @@ def copy(dst, src, nbytes: int | None = None, stream=None) -> None:
     if nbytes is None:
         nbytes = src.numel() * src.element_size()
     _check(lib().pyrit_copy(_dev_ptr(dst), _dev_ptr(src), nbytes, _stream_handle(stream)))
+
+
+def to_sliced(w: int, symbols, sliced, n_symbols: int | None = None, pitch: int = 0,
+              stream=None) -> None:
+    """Symbol-major block (one byte per symbol for w <= 8, one 16-bit word
+    for larger w) -> bit-sliced block of w slices (see pyrit_to_sliced)."""
+    if n_symbols is None:
+        n_symbols = symbols.numel() * symbols.element_size() // (1 if w <= 8 else 2)
+    _check(lib().pyrit_to_sliced(w, _dev_ptr(symbols), n_symbols, _dev_ptr(sliced), pitch,
+                                 _stream_handle(stream)))
+
+
+def from_sliced(w: int, sliced, symbols, n_symbols: int | None = None, pitch: int = 0,
+                stream=None) -> None:
+    """Bit-sliced block -> symbol-major block (inverse of `to_sliced`)."""
+    if n_symbols is None:
+        n_symbols = symbols.numel() * symbols.element_size() // (1 if w <= 8 else 2)
+    _check(lib().pyrit_from_sliced(w, _dev_ptr(sliced), pitch, n_symbols, _dev_ptr(symbols),
+                                   _stream_handle(stream)))

@@ -42,6 +42,8 @@ SIGNATURES = {
     "pyrit_decode": (c_int, [c_vp, c_vp, c_int, c_vp, c_size, c_vp]),
     "pyrit_fill_random": (c_int, [c_vp, c_size, c_size, c_u64, c_vp]),
     "pyrit_copy": (c_int, [c_vp, c_vp, c_size, c_vp]),
+    "pyrit_to_sliced": (c_int, [c_int, c_vp, c_size, c_vp, c_size, c_vp]),
+    "pyrit_from_sliced": (c_int, [c_int, c_vp, c_size, c_size, c_vp, c_vp]),
     "pyrit_batch_create": (c_int, [c_vp, c_int, c_vp, P(c_vp)]),
     "pyrit_batch_launch": (c_int, [c_vp, c_vp]),
     "pyrit_batch_launch_direct": (c_int, [c_vp, c_vp]),

@@ -21,6 +21,7 @@ SOURCES = [
     "serve.cpp",
     "device_api.hip",
     "batch.hip",
+    "transpose.hip",
     "plain_ring0.hip",
     "plain_ring1.hip",
     "plain_ring2.hip",

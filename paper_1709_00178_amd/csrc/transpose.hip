@@ -1,0 +1,185 @@
+// Symbol-major <-> bit-sliced block layout, the steps either side of the
+// coding path when data arrives as ordinary GF(2^w) symbols.
+//
+// Symbol s of a block (one byte for w <= 8, one little-endian 16-bit word for
+// 8 < w <= 16) maps to bit s mod 8 of byte s div 8 of each slice: bit t of the
+// symbol lives in slice t.  This is the bit-slice view the coding kernels and
+// the oracle use (a block as w chunks, Sec. III).
+//
+// One lane handles 32 consecutive symbols: 8 of them fill one byte of every
+// slice, so the lane writes (or reads) one 32-bit word per slice and the 64
+// lanes of a wave cover 256 contiguous bytes of each slice.  The byte-to-slice
+// reshuffle of 8 symbols is an 8 x 8 bit-matrix transpose done with three
+// masked delta swaps on a 64-bit word (an involution, so both directions use
+// it).
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+
+namespace pyrit {
+namespace {
+
+constexpr int kTransposeWG = 256;
+
+// Bit (r, c) of the 8 x 8 matrix whose row r is byte r of x moves to (c, r).
+__device__ __forceinline__ uint64_t transpose8(uint64_t x) {
+  uint64_t t;
+  t = (x ^ (x >> 7)) & 0x00AA00AA00AA00AAull;
+  x = x ^ t ^ (t << 7);
+  t = (x ^ (x >> 14)) & 0x0000CCCC0000CCCCull;
+  x = x ^ t ^ (t << 14);
+  t = (x ^ (x >> 28)) & 0x00000000F0F0F0F0ull;
+  x = x ^ t ^ (t << 28);
+  return x;
+}
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// BYTES = bytes per symbol (1 or 2).  Lane g: symbols 32g .. 32g+31.
+template <int BYTES>
+__global__ __launch_bounds__(kTransposeWG) void to_sliced_kernel(const uint8_t *sym, uint8_t *out,
+                                                                   uint32_t w, uint32_t pitch,
+                                                                   uint32_t lanes) {
+  const uint32_t g = blockIdx.x * kTransposeWG + threadIdx.x;
+  if (g >= lanes) return;
+  // 32 symbols = 32 * BYTES bytes as 64-bit words: word q holds symbols
+  // 8q/BYTES ..; for BYTES = 2, byte 2i is the low half of symbol i.
+  uint64_t v[4 * BYTES];
+  const u32x4 *src = (const u32x4 *)(sym + (size_t)g * 32 * BYTES);
+#pragma unroll
+  for (int i = 0; i < 2 * BYTES; ++i) {
+    const u32x4 x = __builtin_nontemporal_load(src + i);
+    v[2 * i] = ((uint64_t)x.y << 32) | x.x;
+    v[2 * i + 1] = ((uint64_t)x.w << 32) | x.z;
+  }
+  // lo[q], hi[q]: the low / high bytes of symbols 8q .. 8q+7, one per byte
+  uint64_t lo[4], hi[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if constexpr (BYTES == 1) {
+      lo[q] = transpose8(v[q]);
+      hi[q] = 0;
+    } else {
+      // symbols 8q .. 8q+7 are words 2q and 2q+1: split low and high bytes
+      const uint64_t a = v[2 * q], b = v[2 * q + 1];
+      uint64_t l = 0, h = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        l |= ((a >> (16 * i)) & 0xFFull) << (8 * i);
+        l |= ((b >> (16 * i)) & 0xFFull) << (8 * (i + 4));
+        h |= ((a >> (16 * i + 8)) & 0xFFull) << (8 * i);
+        h |= ((b >> (16 * i + 8)) & 0xFFull) << (8 * (i + 4));
+      }
+      lo[q] = transpose8(l);
+      hi[q] = transpose8(h);
+    }
+  }
+  // slice t word = byte t of lo[0..3] (or byte t-8 of hi[0..3])
+  uint8_t *dst = out + (size_t)g * 4;
+  for (uint32_t t = 0; t < w; ++t) {
+    uint32_t word = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint64_t src8 = t < 8 ? lo[q] : hi[q];
+      word |= (uint32_t)((src8 >> (8 * (t & 7))) & 0xFFull) << (8 * q);
+    }
+    *(uint32_t *)(dst + (size_t)t * pitch) = word;
+  }
+}
+
+template <int BYTES>
+__global__ __launch_bounds__(kTransposeWG) void from_sliced_kernel(const uint8_t *in, uint8_t *sym,
+                                                                     uint32_t w, uint32_t pitch,
+                                                                     uint32_t lanes) {
+  const uint32_t g = blockIdx.x * kTransposeWG + threadIdx.x;
+  if (g >= lanes) return;
+  uint64_t lo[4] = {0, 0, 0, 0}, hi[4] = {0, 0, 0, 0};
+  const uint8_t *src = in + (size_t)g * 4;
+  for (uint32_t t = 0; t < w; ++t) {
+    const uint32_t word = __builtin_nontemporal_load((const uint32_t *)(src + (size_t)t * pitch));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint64_t b = (word >> (8 * q)) & 0xFFu;
+      if (t < 8)
+        lo[q] |= b << (8 * t);
+      else
+        hi[q] |= b << (8 * (t - 8));
+    }
+  }
+  uint64_t v[4 * BYTES];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint64_t l = transpose8(lo[q]);
+    if constexpr (BYTES == 1) {
+      v[q] = l;
+    } else {
+      const uint64_t h = transpose8(hi[q]);
+      uint64_t a = 0, b = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a |= ((l >> (8 * i)) & 0xFFull) << (16 * i);
+        a |= ((h >> (8 * i)) & 0xFFull) << (16 * i + 8);
+        b |= ((l >> (8 * (i + 4))) & 0xFFull) << (16 * i);
+        b |= ((h >> (8 * (i + 4))) & 0xFFull) << (16 * i + 8);
+      }
+      v[2 * q] = a;
+      v[2 * q + 1] = b;
+    }
+  }
+  u32x4 *dst = (u32x4 *)(sym + (size_t)g * 32 * BYTES);
+#pragma unroll
+  for (int i = 0; i < 2 * BYTES; ++i) {
+    u32x4 x;
+    x.x = (uint32_t)v[2 * i];
+    x.y = (uint32_t)(v[2 * i] >> 32);
+    x.z = (uint32_t)v[2 * i + 1];
+    x.w = (uint32_t)(v[2 * i + 1] >> 32);
+    dst[i] = x;
+  }
+}
+
+int check_transpose(int w, const void *a, const void *b, size_t n_symbols, size_t *pitch) {
+  if (w < 1 || w > 16 || !a || !b) return PYRIT_EINVAL;
+  if (n_symbols == 0 || n_symbols % 512 != 0 || n_symbols / 32 > 0xFFFFFFFFull) return PYRIT_EINVAL;
+  if (((uintptr_t)a & 15u) || ((uintptr_t)b & 15u)) return PYRIT_EALIGN;
+  return check_slices(w, n_symbols / 8, pitch);
+}
+
+}  // namespace
+}  // namespace pyrit
+
+using namespace pyrit;
+
+extern "C" {
+
+int pyrit_to_sliced(int w, const void *symbols, size_t n_symbols, uint8_t *sliced, size_t slice_pitch,
+                    void *stream) {
+  int rc = check_transpose(w, symbols, sliced, n_symbols, &slice_pitch);
+  if (rc) return rc;
+  const uint32_t lanes = (uint32_t)(n_symbols / 32);
+  const dim3 grid((lanes + kTransposeWG - 1) / kTransposeWG);
+  if (w <= 8)
+    hipLaunchKernelGGL(to_sliced_kernel<1>, grid, dim3(kTransposeWG), 0, (hipStream_t)stream,
+                       (const uint8_t *)symbols, sliced, (uint32_t)w, (uint32_t)slice_pitch, lanes);
+  else
+    hipLaunchKernelGGL(to_sliced_kernel<2>, grid, dim3(kTransposeWG), 0, (hipStream_t)stream,
+                       (const uint8_t *)symbols, sliced, (uint32_t)w, (uint32_t)slice_pitch, lanes);
+  return hipGetLastError() == hipSuccess ? PYRIT_OK : PYRIT_EHIP;
+}
+
+int pyrit_from_sliced(int w, const uint8_t *sliced, size_t slice_pitch, size_t n_symbols, void *symbols,
+                      void *stream) {
+  int rc = check_transpose(w, sliced, symbols, n_symbols, &slice_pitch);
+  if (rc) return rc;
+  const uint32_t lanes = (uint32_t)(n_symbols / 32);
+  const dim3 grid((lanes + kTransposeWG - 1) / kTransposeWG);
+  if (w <= 8)
+    hipLaunchKernelGGL(from_sliced_kernel<1>, grid, dim3(kTransposeWG), 0, (hipStream_t)stream,
+                       sliced, (uint8_t *)symbols, (uint32_t)w, (uint32_t)slice_pitch, lanes);
+  else
+    hipLaunchKernelGGL(from_sliced_kernel<2>, grid, dim3(kTransposeWG), 0, (hipStream_t)stream,
+                       sliced, (uint8_t *)symbols, (uint32_t)w, (uint32_t)slice_pitch, lanes);
+  return hipGetLastError() == hipSuccess ? PYRIT_OK : PYRIT_EHIP;
+}
+
+}  // extern "C"

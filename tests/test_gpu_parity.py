@@ -353,3 +353,74 @@ def test_slice_pitch_plain_and_batched(w, n, p, pad):
     with pytest.raises(P.PyritError):
         plan.encode(data, code[k:], st.S, pitch=st.S + 32)
     del torch
+
+
+# Symbol-major <-> bit-sliced conversions on the device against the oracle's.
+# 512 * 257 symbols: 4112 lanes, not a multiple of the 256-lane workgroup.
+N_SYM = 512 * 257
+
+
+@pytest.mark.parametrize("w", [1, 4, 6, 8, 10, 16])
+@pytest.mark.parametrize("extra_pitch", [0, 192])
+def test_to_and_from_sliced(w, extra_pitch):
+    torch = torch_mod()
+    rng = np.random.Generator(np.random.PCG64(w * 10 + extra_pitch))
+    dt = np.uint8 if w <= 8 else np.uint16
+    sym = rng.integers(0, 1 << (8 if w <= 8 else 16), N_SYM).astype(dt)  # high bits set too
+    S = N_SYM // 8
+    pitch = S + extra_pitch
+    dsym = torch.from_numpy(sym.view(np.uint8).copy()).cuda()
+    dsl = dev_empty(w * pitch)
+    dsl.fill_(0x77)
+    P.to_sliced(w, dsym, dsl, n_symbols=N_SYM, pitch=pitch if extra_pitch else 0)
+    back = dev_empty(sym.nbytes)
+    back.fill_(0xEE)
+    P.from_sliced(w, dsl, back, n_symbols=N_SYM, pitch=pitch if extra_pitch else 0)
+    sync()
+    want = oracle.to_sliced(w, sym.astype(np.uint32) & ((1 << w) - 1)).reshape(w, S)
+    got = to_host(dsl).reshape(w, pitch)[:, :S]
+    assert np.array_equal(got, want)
+    masked = (sym.astype(np.uint32) & ((1 << w) - 1)).astype(dt)
+    assert np.array_equal(to_host(back).view(dt), masked)
+
+
+def test_symbols_to_parity_symbols_end_to_end():
+    """GF(2^8) k=10 m=4: symbols -> slices -> encode -> parity symbols equals
+    the symbol-by-symbol product with the oracle's multiply."""
+    torch = torch_mod()
+    w, n, p, k, m = 8, 17, 0x139, 10, 4
+    nsym = 512 * 64
+    S = nsym // 8
+    rng = np.random.Generator(np.random.PCG64(77))
+    data = [rng.integers(0, 256, nsym).astype(np.uint8) for _ in range(k)]
+    plan = P.Plan(w, n, p, k, m)
+    sliced = [dev_empty(w * S) for _ in range(k + m)]
+    for j in range(k):
+        P.to_sliced(w, torch.from_numpy(data[j]).cuda(), sliced[j])
+    plan.encode(sliced[:k], sliced[k:], S)
+    out = [dev_empty(nsym) for _ in range(m)]
+    for i in range(m):
+        P.from_sliced(w, sliced[k + i], out[i])
+    sync()
+    f = oracle.Field(w, p)
+    for i in range(m):
+        want = np.zeros(nsym, dtype=np.uint32)
+        for j in range(k):
+            want ^= f.mul_many(np.full(nsym, plan.G[i, j], dtype=np.uint32), data[j])
+        assert np.array_equal(to_host(out[i]), want.astype(np.uint8)), i
+
+
+def test_sliced_conversion_errors():
+    a, b = dev_empty(8192), dev_empty(8192)
+    for bad in [dict(w=0), dict(w=17), dict(n_symbols=500), dict(n_symbols=0)]:
+        args = dict(w=8, n_symbols=512)
+        args.update(bad)
+        with pytest.raises(P.PyritError) as e:
+            P.to_sliced(args["w"], a, b, n_symbols=args["n_symbols"])
+        assert e.value.code == -1, bad
+    with pytest.raises(P.PyritError) as e:
+        P.to_sliced(8, a.data_ptr() + 4, b, n_symbols=512)
+    assert e.value.code == -8
+    with pytest.raises(P.PyritError) as e:
+        P.from_sliced(8, a, b, n_symbols=512, pitch=96)
+    assert e.value.code in (-1, -8)

@@ -330,3 +330,39 @@ def test_oracle_on_workload_generator_bytes():
         f.decode(C, list(er), blocks, st.S, nthreads=4)
         for a, b in zip(blocks, code):
             assert np.array_equal(a, b)
+
+
+# Symbol-major <-> bit-sliced layout (the steps either side of the coding path).
+
+def test_to_sliced_against_loop_definition():
+    rng = np.random.Generator(np.random.PCG64(21))
+    for w in (4, 8, 10, 16):
+        sym = rng.integers(0, 1 << w, 24)
+        got = oracle.to_sliced(w, sym).reshape(w, 3)
+        for s in range(24):
+            for t in range(w):
+                assert (int(got[t, s // 8]) >> (s % 8)) & 1 == (int(sym[s]) >> t) & 1
+
+
+@pytest.mark.parametrize("w", [1, 4, 6, 8, 10, 16])
+def test_sliced_roundtrip(w):
+    rng = np.random.Generator(np.random.PCG64(w))
+    sym = rng.integers(0, 1 << w, 8 * 40)
+    assert np.array_equal(oracle.from_sliced(w, oracle.to_sliced(w, sym), sym.size), sym)
+
+
+@pytest.mark.parametrize("w,p", [(8, 0x139), (10, 0x7FF), (4, 0x1F)])
+def test_sliced_encode_equals_symbolwise_products(w, p):
+    """Encoding in the bit-sliced layout and converting back gives the plain
+    symbol-by-symbol matrix product (products from the schoolbook multiply)."""
+    f = oracle.Field(w, p)
+    k, m, n = 5, 3, 8 * 64
+    C = f.cauchy(k, m)
+    rng = np.random.Generator(np.random.PCG64(w + 7))
+    data = [rng.integers(0, 1 << w, n) for _ in range(k)]
+    par = f.encode(C, [oracle.to_sliced(w, d) for d in data], n // 8)
+    for i in range(m):
+        want = np.zeros(n, dtype=np.int64)
+        for j in range(k):
+            want ^= sb.mul(np.full(n, int(C[i, j])), data[j], w, p)
+        assert np.array_equal(oracle.from_sliced(w, par[i], n).astype(np.int64), want), i
