@@ -4,7 +4,7 @@ same kernel, both timed, the faster runs the steps), beside the plain
 per-stripe kernel, decode, the 256-stripe and 4096-stripe batches, the
 HBM roofline and the CPU oracle.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--only c1,c1s,layout,c2,c3,c4]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--only c1,c1s,layout,shapes,c2,c3,c4]
 
 Prints ONE JSON line.  A step is one encode of the whole stripe (10 data
 blocks of 64 MiB, 4 parity blocks of 64 MiB), inputs already resident in HBM.
@@ -370,6 +370,33 @@ def bench_layout(args, stream, out, log):
     torch.cuda.empty_cache()
 
 
+def bench_paper_shapes(args, stream, out, log):
+    """The code shapes of the paper's Sec. IV figures, (12,8) over GF(2^4) and
+    (60,40), (60,20) over GF(2^6), with 1 MiB blocks, under the embedding and
+    the parity transform (one plain encode per call; passes of at most four
+    parity blocks each re-read the data blocks)."""
+    import torch
+
+    import paper_1709_00178_amd as P
+    from paper_1709_00178_amd import workloads as W
+    res = {}
+    for (w, n, p), k, m in (((4, 5, 0x1F), 8, 4), ((6, 9, 0x49), 40, 20), ((6, 9, 0x49), 20, 40)):
+        st = W.Stripe(w, n, p, k=k, m=m, B=1 << 20, seed=W.BASE_SEED + 9)
+        arena = Arena(arena_bytes([st], BLOCK_SKEW), BLOCK_SKEW)
+        bl = stripe_buffers(st, arena)
+        row = {"w": w, "k": k, "m": m, "block_bytes": st.B}
+        for tr in ("embedding", "parity"):
+            plan = P.Plan(w, n, p, k, m, transform=tr)
+            fn = lambda: plan.encode(bl[:k], bl[k:], st.S, stream=stream)
+            fn()
+            ms = min(batch_time_ms(fn, 10, stream) for _ in range(2))
+            row[tr] = {"GBps_data": round(k * st.B / (ms * 1e-3) / 1e9, 1), "ms": round(ms, 4)}
+        res[f"({k + m},{k}) GF(2^{w})"] = row
+        del arena, bl
+    out["paper_code_shapes"] = res
+    torch.cuda.empty_cache()
+
+
 def bench_c2(args, stream, out, log):
     import torch
 
@@ -492,9 +519,10 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", default="c1,c1s,layout,c2,c3,c4",
+    ap.add_argument("--only", default="c1,c1s,layout,shapes,c2,c3,c4",
                     help="comma list of c1 (headline stripe), c1s (64 stripes of the same "
-                         "code), layout (symbol <-> bit-sliced conversion), c2, c3, c4")
+                         "code), layout (symbol <-> bit-sliced conversion), shapes (the "
+                         "paper's code shapes, both transforms), c2, c3, c4")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported. Stripes (or "
@@ -531,6 +559,8 @@ def main():
         bench_c1_stripes(args, stream, out, log)
     if "layout" in only:
         bench_layout(args, stream, out, log)
+    if "shapes" in only:
+        bench_paper_shapes(args, stream, out, log)
     if "c2" in only:
         bench_c2(args, stream, out, log)
     if "c3" in only:

@@ -117,6 +117,20 @@ int pyrit_cauchy_light(int w, int n, uint32_t p, int k, int m, uint16_t *G, uint
 /* -------------------------------------------------------------------- plans */
 typedef struct pyrit_plan pyrit_plan;
 
+/* How data enter and leave the ring.
+ *   EMBEDDING (Sec. II-C.2, II-D.2): a symbol is padded with n - w zero
+ *     coefficients; results are reduced modulo p.  The code is exactly the
+ *     field code [I_k; G].
+ *   PARITY (Sec. II-C.1, II-D.1): a symbol b enters as the element of the
+ *     ideal isomorphic to the field whose low w coefficients are b (for the
+ *     AOP, one parity bit; for x^6+x^3+1, three interleaved parity bits);
+ *     results leave by dropping the n - w high coefficients.  This is a
+ *     different code: with psi(b) = phi_P(b) mod p, parity_i =
+ *     psi^-1(sum_j G[i][j] psi(d_j)) symbol by symbol, still MDS; encoder and
+ *     decoder must both use it.  Kernels exist for the AOP rings (4,5),
+ *     (10,11) and the ESP ring (6,9). */
+enum { PYRIT_TRANSFORM_EMBEDDING = 0, PYRIT_TRANSFORM_PARITY = 1 };
+
 /* Build the lifted XOR schedule of the systematic code [I_k; G] (G is the
  * m x k row-major parity part, host memory, copied).  Validates the ring
  * (pyrit_ring_check), 1 <= k <= PYRIT_KMAX, 1 <= m <= PYRIT_MMAX,
@@ -125,6 +139,15 @@ typedef struct pyrit_plan pyrit_plan;
  * PYRIT_EUNSUPPORTED.  *out receives the plan. */
 int pyrit_plan_create(int w, int n, uint32_t p, int k, int m, const uint16_t *G,
                       pyrit_plan **out);
+
+/* pyrit_plan_create with a choice of transform (PYRIT_TRANSFORM_*); an
+ * unknown transform is PYRIT_EINVAL.  pyrit_plan_create is the EMBEDDING
+ * case.  Decoding with a PARITY plan undoes the PARITY code. */
+int pyrit_plan_create_ex(int w, int n, uint32_t p, int k, int m, const uint16_t *G, int transform,
+                         pyrit_plan **out);
+
+/* The plan's transform (PYRIT_TRANSFORM_*). */
+int pyrit_plan_transform(const pyrit_plan *plan, int *transform);
 
 /* Release a plan and its device copies.  NULL is ignored.  The caller must
  * ensure no stream still runs work that uses the plan. */

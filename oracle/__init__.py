@@ -197,3 +197,73 @@ def from_sliced(w: int, sliced, n: int) -> np.ndarray:
         for b in range(8):
             sym[:, b] |= ((blk[t] >> b) & 1) << t
     return sym.reshape(-1).astype(np.uint16)
+
+
+# ---------------------------------------------------------------------------
+# The parity transform (Sec. II-C.1 for the all-one polynomial, Sec. II-D.1
+# for the equally spaced x^6+x^3+1).  A symbol b enters the ring as the one
+# element of the ideal isomorphic to the field whose low w coefficients are
+# b (the ideal is generated by h = (x^n + 1) / p: for the AOP the even-weight
+# words, for the ESP three interleaved even-weight words); results leave the
+# ring by dropping the n - w high coefficients.  This is a bijection, not the
+# field isomorphism, so the code differs from [I; C]: with
+# psi(b) = phi_P(b) mod p, parity_i = psi^-1(sum_j C[i][j] psi(d_j)).
+
+def _poly_mod(a: int, m: int) -> int:
+    dm = m.bit_length() - 1
+    while a and a.bit_length() - 1 >= dm:
+        a ^= m << (a.bit_length() - 1 - dm)
+    return a
+
+
+def _poly_div(a: int, m: int) -> int:
+    q, dm = 0, m.bit_length() - 1
+    while a and a.bit_length() - 1 >= dm:
+        s = a.bit_length() - 1 - dm
+        q |= 1 << s
+        a ^= m << s
+    assert a == 0, "p must divide x^n + 1"
+    return q
+
+
+def parity_embed_table(w: int, n: int, p: int) -> np.ndarray:
+    """phi_P(b) for every symbol b: b plus the high coefficients q (deg q <
+    n - w) that make it a multiple of h = (x^n + 1) / p, found by search."""
+    h = _poly_div((1 << n) | 1, p)
+    out = np.zeros(1 << w, dtype=np.uint32)
+    for b in range(1 << w):
+        hits = [q for q in range(1 << (n - w)) if _poly_mod(b | (q << w), h) == 0]
+        assert len(hits) == 1
+        out[b] = b | (hits[0] << w)
+    return out
+
+
+def psi_table(w: int, n: int, p: int) -> np.ndarray:
+    """psi(b) = phi_P(b) mod p for every symbol b."""
+    return np.array([_poly_mod(int(a), p) for a in parity_embed_table(w, n, p)], dtype=np.uint32)
+
+
+def _map_symbols(w: int, block: np.ndarray, table: np.ndarray) -> np.ndarray:
+    n = block.size // w * 8
+    return to_sliced(w, table[from_sliced(w, block, n)])
+
+
+def encode_parity_transform(f: "Field", n: int, C, data, S: int):
+    """Parity blocks of the parity-transform code over ring R_{2,n}."""
+    psi = psi_table(f.w, n, f.p)
+    inv = np.argsort(psi).astype(np.uint32)
+    tdata = [_map_symbols(f.w, np.ascontiguousarray(d), psi) for d in data]
+    return [_map_symbols(f.w, b, inv) for b in f.encode(C, tdata, S)]
+
+
+def decode_parity_transform(f: "Field", n: int, C, erased, blocks, S: int):
+    """Overwrite the erased blocks of a parity-transform codeword in place."""
+    psi = psi_table(f.w, n, f.p)
+    inv = np.argsort(psi).astype(np.uint32)
+    er = set(erased)
+    tb = [b if i in er else _map_symbols(f.w, b, psi) for i, b in enumerate(blocks)]
+    tb = [np.ascontiguousarray(b) for b in tb]
+    f.decode(C, list(erased), tb, S)
+    for e in erased:
+        blocks[e][:] = _map_symbols(f.w, tb[e], inv)
+    return blocks

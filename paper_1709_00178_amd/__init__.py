@@ -117,18 +117,27 @@ class Plan:
     """A code [I_k; G] over GF(2^w) = F_2[x]/(p), lifted into R_{2,n}.
 
     ``G`` (m x k) defaults to the plain Cauchy matrix 1 / (i + m + j).
+    ``transform``: "embedding" (the field code [I; G]) or "parity" (the
+    paper's parity transform, a different MDS code; see pyrit.h).
     """
 
-    def __init__(self, w: int, n: int, p: int, k: int, m: int, G=None):
+    TRANSFORMS = {"embedding": 0, "parity": 1}
+
+    def __init__(self, w: int, n: int, p: int, k: int, m: int, G=None,
+                 transform: str = "embedding"):
         if G is None:
             G = cauchy(w, p, k, m)
         G = np.ascontiguousarray(G, dtype=np.uint16)
         if G.shape != (m, k):
             raise ValueError(f"G must be {m}x{k}")
+        if transform not in self.TRANSFORMS:
+            raise ValueError(f"transform must be one of {sorted(self.TRANSFORMS)}")
         h = ctypes.c_void_p()
-        _check(lib().pyrit_plan_create(w, n, p, k, m, G.ctypes.data, ctypes.byref(h)))
+        _check(lib().pyrit_plan_create_ex(w, n, p, k, m, G.ctypes.data, self.TRANSFORMS[transform],
+                                          ctypes.byref(h)))
         self._h = h
         self.w, self.n, self.p, self.k, self.m = w, n, p, k, m
+        self.transform = transform
         self.G = G.copy()
 
     def close(self):

@@ -27,6 +27,9 @@ SOURCES = [
     "plain_ring2.hip",
     "plain_ring3.hip",
     "plain_ring4.hip",
+    "plain_ring5.hip",
+    "plain_ring6.hip",
+    "plain_ring7.hip",
 ]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", f"-I{os.path.join(HERE, '..', 'include')}"]

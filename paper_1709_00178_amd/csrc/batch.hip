@@ -60,7 +60,7 @@ struct BatchArgs {
 // Lane width per ring inside the batch kernels: the widest that keeps every
 // ring at or below the (8,17) ring's register count (about 90 VGPRs with four
 // outputs), so one kernel holds all rings at five waves per SIMD.
-constexpr int kBatchV[kNumRings] = {2, 1, 1, 1, 1};
+constexpr int kBatchV[kNumRings] = {2, 1, 1, 1, 1, 2, 1, 1};
 
 // kBatchV packed four bits per ring, so a run-time ring id maps to its lane
 // width with a shift instead of a table load.
@@ -122,7 +122,7 @@ template <int RING>
 __device__ __forceinline__ void run_tile(const AS4 PassDesc *pd, uint32_t col0, uint32_t col1,
                                          uint32_t lane) {
   constexpr RingDesc R = kRings[RING];
-  dev::code_tile<R.w, R.n, R.p, kMaxOut, kBatchV[RING]>(table_src(pd), col0, col1, lane);
+  dev::code_tile<R.w, R.n, R.p, kMaxOut, kBatchV[RING], R.parity>(table_src(pd), col0, col1, lane);
 }
 
 // LDS exchange of the split-K grid kernel, in dwords: kMaxOut outputs x the
@@ -141,7 +141,7 @@ __device__ __forceinline__ void run_chunk(const PassDesc &pd, uint32_t base, uin
   typedef typename dev::Vec<V>::T T;
   const TableSrc src = table_src(pd);
   const uint32_t col = base + lane * 4u * V;
-  dev::code_column<R.w, R.n, R.p, kMaxOut, V, KS>(src, col, col < src.S(), part, (T *)xch);
+  dev::code_column<R.w, R.n, R.p, kMaxOut, V, KS, R.parity>(src, col, col < src.S(), part, (T *)xch);
 }
 
 __device__ __forceinline__ void code_item(const AS4 PassDesc *passes, const AS4 WorkItem *it,
@@ -154,6 +154,9 @@ __device__ __forceinline__ void code_item(const AS4 PassDesc *passes, const AS4 
     case 2: run_tile<2>(pd, c0, c1, lane); break;
     case 3: run_tile<3>(pd, c0, c1, lane); break;
     case 4: run_tile<4>(pd, c0, c1, lane); break;
+    case 5: run_tile<5>(pd, c0, c1, lane); break;
+    case 6: run_tile<6>(pd, c0, c1, lane); break;
+    case 7: run_tile<7>(pd, c0, c1, lane); break;
     default: break;
   }
 }
@@ -206,6 +209,9 @@ __global__ __launch_bounds__(WG) void batch_grid_kernel(const BatchArgs a) {
     case 2: run_chunk<2, KS>(pd, base, lane, part, xch); break;
     case 3: run_chunk<3, KS>(pd, base, lane, part, xch); break;
     case 4: run_chunk<4, KS>(pd, base, lane, part, xch); break;
+    case 5: run_chunk<5, KS>(pd, base, lane, part, xch); break;
+    case 6: run_chunk<6, KS>(pd, base, lane, part, xch); break;
+    case 7: run_chunk<7, KS>(pd, base, lane, part, xch); break;
     default: break;
   }
 }

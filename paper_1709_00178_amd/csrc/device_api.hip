@@ -28,6 +28,9 @@ int launch_pass(int ring, int nout, int vec_bytes, const PassArgs &a, void *stre
     case 2: return launch_plain_ring<2>(nout, vec_bytes, a, st);
     case 3: return launch_plain_ring<3>(nout, vec_bytes, a, st);
     case 4: return launch_plain_ring<4>(nout, vec_bytes, a, st);
+    case 5: return launch_plain_ring<5>(nout, vec_bytes, a, st);
+    case 6: return launch_plain_ring<6>(nout, vec_bytes, a, st);
+    case 7: return launch_plain_ring<7>(nout, vec_bytes, a, st);
     default: return PYRIT_EUNSUPPORTED;
   }
 }

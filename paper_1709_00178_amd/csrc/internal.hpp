@@ -17,19 +17,28 @@ constexpr int kMaxOut = 4;
 
 // Rings with a device kernel.  The kernels are templates on (w, n, p), so the
 // reduction modulo p and every rotation index are compile-time constants.
+// `parity` selects the parity transform (Sec. II-C.1, II-D.1) in place of the
+// embedding transform (Sec. II-C.2, II-D.2): data enter the ring with n - w
+// parity slices instead of zero slices, and results leave it by dropping
+// those slices instead of reducing modulo p.
 struct RingDesc {
   int w, n;
   uint32_t p;
+  bool parity;
 };
-constexpr int kNumRings = 5;
+constexpr int kNumRings = 8;
 constexpr RingDesc kRings[kNumRings] = {
-    {4, 5, 0x1Fu},     // all-one polynomial of degree 4 (Sec. II-C)
-    {8, 17, 0x139u},   // x^8+x^5+x^4+x^3+1, divides x^17+1
-    {8, 17, 0x1D7u},   // x^8+x^7+x^6+x^4+x^2+x+1, the other factor
-    {10, 11, 0x7FFu},  // all-one polynomial of degree 10
-    {6, 9, 0x49u},     // equally spaced x^6+x^3+1 (Sec. II-D)
+    {4, 5, 0x1Fu, false},     // all-one polynomial of degree 4 (Sec. II-C)
+    {8, 17, 0x139u, false},   // x^8+x^5+x^4+x^3+1, divides x^17+1
+    {8, 17, 0x1D7u, false},   // x^8+x^7+x^6+x^4+x^2+x+1, the other factor
+    {10, 11, 0x7FFu, false},  // all-one polynomial of degree 10
+    {6, 9, 0x49u, false},     // equally spaced x^6+x^3+1 (Sec. II-D)
+    {4, 5, 0x1Fu, true},      // the AOP and ESP rings again, parity transform
+    {10, 11, 0x7FFu, true},
+    {6, 9, 0x49u, true},
 };
-int ring_id(int w, int n, uint32_t p);  // -1 when no kernel exists
+// -1 when no kernel exists; transform: PYRIT_TRANSFORM_*
+int ring_id(int w, int n, uint32_t p, int transform = PYRIT_TRANSFORM_EMBEDDING);
 
 // Arguments of one coding pass: outputs out[r] (r < nout) are
 // sum_j lift[j][r] (*) in[j] in the ring, reduced mod p.
@@ -66,6 +75,7 @@ struct pyrit_plan {
   uint32_t p = 0;
   int k = 0, m = 0;
   int ring = -1;
+  int transform = PYRIT_TRANSFORM_EMBEDDING;
   std::vector<uint16_t> G;  // m x k
   std::vector<uint32_t> L;  // m x k lifted
   int weight = 0;

@@ -17,7 +17,7 @@ __global__ __launch_bounds__(kPlainWG) void plain_pass_kernel(const PassArgs a) 
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t part = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t col = (blockIdx.x * 64u + lane) * (4u * V);
-  dev::code_column<R.w, R.n, R.p, MO, V, 2>(dev::KernargSrc{a}, col, col < a.S, part, xch);
+  dev::code_column<R.w, R.n, R.p, MO, V, 2, R.parity>(dev::KernargSrc{a}, col, col < a.S, part, xch);
 }
 
 template <int RING, int MO, int V>

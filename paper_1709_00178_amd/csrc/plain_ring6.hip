@@ -1,0 +1,6 @@
+// Instantiates the plain kernels of ring 6 (one file per ring: parallel builds).
+#include "plain_impl.hpp"
+
+namespace pyrit {
+template int launch_plain_ring<6>(int, int, const PassArgs &, hipStream_t);
+}

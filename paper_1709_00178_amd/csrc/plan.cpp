@@ -11,9 +11,11 @@
 
 namespace pyrit {
 
-int ring_id(int w, int n, uint32_t p) {
+int ring_id(int w, int n, uint32_t p, int transform) {
+  const bool parity = transform == PYRIT_TRANSFORM_PARITY;
   for (int i = 0; i < kNumRings; ++i)
-    if (kRings[i].w == w && kRings[i].n == n && kRings[i].p == p) return i;
+    if (kRings[i].w == w && kRings[i].n == n && kRings[i].p == p && kRings[i].parity == parity)
+      return i;
   return -1;
 }
 
@@ -289,6 +291,13 @@ int pyrit_cauchy_light(int w, int n, uint32_t p, int k, int m, uint16_t *G, uint
 
 int pyrit_plan_create(int w, int n, uint32_t p, int k, int m, const uint16_t *G,
                       pyrit_plan **out) {
+  return pyrit_plan_create_ex(w, n, p, k, m, G, PYRIT_TRANSFORM_EMBEDDING, out);
+}
+
+int pyrit_plan_create_ex(int w, int n, uint32_t p, int k, int m, const uint16_t *G, int transform,
+                         pyrit_plan **out) {
+  if (transform != PYRIT_TRANSFORM_EMBEDDING && transform != PYRIT_TRANSFORM_PARITY)
+    return PYRIT_EINVAL;
   if (!out || !G) return PYRIT_EINVAL;
   *out = nullptr;
   int rc = pyrit_ring_check(w, n, p);
@@ -304,7 +313,8 @@ int pyrit_plan_create(int w, int n, uint32_t p, int k, int m, const uint16_t *G,
   pl->p = p;
   pl->k = k;
   pl->m = m;
-  pl->ring = ring_id(w, n, p);
+  pl->ring = ring_id(w, n, p, transform);
+  pl->transform = transform;
   pl->G.assign(G, G + (size_t)m * k);
   const auto &lt = lift_table(w, n, p);
   pl->L.resize(pl->G.size());
@@ -325,6 +335,12 @@ int pyrit_plan_params(const pyrit_plan *plan, int *w, int *n, uint32_t *p, int *
   if (p) *p = plan->p;
   if (k) *k = plan->k;
   if (m) *m = plan->m;
+  return PYRIT_OK;
+}
+
+int pyrit_plan_transform(const pyrit_plan *plan, int *transform) {
+  if (!plan || !transform) return PYRIT_EINVAL;
+  *transform = plan->transform;
   return PYRIT_OK;
 }
 

@@ -78,6 +78,76 @@ __device__ __forceinline__ void bstore(typename Vec<V>::T x, __amdgpu_buffer_rsr
     __builtin_amdgcn_raw_buffer_store_b128(x, r, voff, soff, kStorePolicy);
 }
 
+// ---- parity transform (Sec. II-C.1, II-D.1), all at compile time --------
+// Carry-less product and remainder of small polynomials (bit i = x^i).
+constexpr uint32_t cl_mul(uint32_t a, uint32_t b) {
+  uint32_t r = 0;
+  for (int i = 0; i < 32; ++i)
+    if (b >> i & 1u) r ^= a << i;
+  return r;
+}
+constexpr int cl_deg(uint32_t a) {
+  int d = -1;
+  for (int i = 0; i < 32; ++i)
+    if (a >> i & 1u) d = i;
+  return d;
+}
+constexpr uint32_t cl_mod(uint32_t a, uint32_t m) {
+  const int dm = cl_deg(m);
+  for (int d = cl_deg(a); d >= dm; d = cl_deg(a)) a ^= m << (d - dm);
+  return a;
+}
+// h = (x^N + 1) / P: the ideal of multiples of h is the copy of the field
+// inside R_{2,N} (the AOP case: h = x + 1, the ESP x^6+x^3+1: h = x^3 + 1).
+constexpr uint32_t ideal_gen(int N, uint32_t P) {
+  uint32_t a = (1u << N) | 1u, q = 0;
+  const int dp = cl_deg(P);
+  for (int d = cl_deg(a); d >= dp; d = cl_deg(a)) {
+    q |= 1u << (d - dp);
+    a ^= P << (d - dp);
+  }
+  return q;
+}
+// The parity transform sends b (deg < W) to b + x^W q with q = b x^-W mod h,
+// the one element of the ideal whose low W coefficients are b.  Bit i of
+// pt_mask(t) is set when coefficient i of b feeds coefficient t (W <= t < N).
+constexpr uint32_t pt_mask(int t, int W, int N, uint32_t P) {
+  const uint32_t h = ideal_gen(N, P);
+  const uint32_t xw = cl_mod(1u << W, h);
+  uint32_t y = 1;
+  for (uint32_t c = 1; c < (1u << (N - W)); ++c)
+    if (cl_mod(cl_mul(c, xw), h) == 1u) y = c;
+  uint32_t mask = 0;
+  for (int i = 0; i < W; ++i)
+    if (cl_mod(cl_mul(1u << i, y), h) >> (t - W) & 1u) mask |= 1u << i;
+  return mask;
+}
+
+template <int W, int N, uint32_t P>
+struct PtMasks {
+  uint32_t m[N > W ? N : 1];
+  constexpr PtMasks() : m() {
+    for (int t = W; t < N; ++t) m[t] = pt_mask(t, W, N, P);
+  }
+};
+
+// Embedded block of the parity transform: the W loaded slices, then the
+// N - W parity slices built from them.
+template <int W, int N, uint32_t P, typename T>
+__device__ __forceinline__ void parity_embed(T (&e)[N], const T (&d)[W]) {
+  constexpr PtMasks<W, N, P> M{};
+#pragma unroll
+  for (int t = 0; t < W; ++t) e[t] = d[t];
+#pragma unroll
+  for (int t = W; t < N; ++t) {
+    T x = (T)0;
+#pragma unroll
+    for (int i = 0; i < W; ++i)
+      if (M.m[t] >> i & 1u) x ^= d[i];
+    e[t] = x;
+  }
+}
+
 // acc[(t + s) mod N] ^= d[t] for t < W and every s >= S0 set in c.
 template <int W, int N, int S0, typename T>
 __device__ __forceinline__ void rot_acc(T (&acc)[N], const T (&d)[W], uint32_t c) {
@@ -101,6 +171,29 @@ __device__ __forceinline__ void reduce_mod_p(T (&acc)[N]) {
     for (int b = 0; b < W; ++b)
       if (red >> b & 1u) acc[b] ^= acc[i];
   }
+}
+
+// One input block into the ring accumulators of MO outputs: embedding
+// transform (the block as is, zero slices implied) or parity transform (the
+// block extended by its parity slices).
+template <int W, int N, uint32_t P, int MO, bool PT, typename T>
+__device__ __forceinline__ void accumulate(T (&acc)[MO][N], const T (&d)[W], const u32x4 &cf) {
+  if constexpr (PT) {
+    T e[N];
+    parity_embed<W, N, P, T>(e, d);
+#pragma unroll
+    for (int r = 0; r < MO; ++r) rot_acc<N, N, 0, T>(acc[r], e, cf[r]);
+  } else {
+#pragma unroll
+    for (int r = 0; r < MO; ++r) rot_acc<W, N, 0, T>(acc[r], d, cf[r]);
+  }
+}
+
+// Ring slices back to field slices: reduction modulo p (embedding transform)
+// or nothing, the high slices being dropped (parity transform).
+template <int W, int N, uint32_t P, bool PT, typename T>
+__device__ __forceinline__ void leave_ring(T (&acc)[N]) {
+  if constexpr (!PT) reduce_mod_p<W, N, P, T>(acc);
 }
 
 // Load the W slices of one block at this lane's column.  bytes == 0 gives an
@@ -129,7 +222,7 @@ __device__ __forceinline__ void load_block(typename Vec<V>::T (&d)[W], const uin
 // Half as many columns are in flight for the same number of waves, which
 // shrinks the set of HBM rows open at once (measured on MI355X: 6.6 -> 7.0
 // TB/s for the 10-in/4-out, 8-slice access pattern).
-template <int W, int N, uint32_t P, int MO, int V, int KS = 1, class Src>
+template <int W, int N, uint32_t P, int MO, int V, int KS = 1, bool PT = false, class Src>
 __device__ __forceinline__ void code_column(const Src &src, uint32_t col, bool live,
                                             uint32_t part = 0,
                                             typename Vec<V>::T *xch = nullptr) {
@@ -168,8 +261,7 @@ __device__ __forceinline__ void code_column(const Src &src, uint32_t col, bool l
       prefetch(q ^ 1, jq + KS, ip);
       ip = src.in(clampj(jq + 2 * KS));
       const u32x4 cn = src.lift4(clampj(jq + KS));
-#pragma unroll
-      for (int r = 0; r < MO; ++r) rot_acc<W, N, 0, T>(acc[r], d[q], cf[r]);
+      accumulate<W, N, P, MO, PT, T>(acc, d[q], cf);
       cf = cn;
     }
   }
@@ -179,7 +271,7 @@ __device__ __forceinline__ void code_column(const Src &src, uint32_t col, bool l
 #pragma unroll
     for (int r = 0; r < MO; ++r) {
       if (r >= src.nout()) break;
-      reduce_mod_p<W, N, P, T>(acc[r]);
+      leave_ring<W, N, P, PT, T>(acc[r]);
       const __amdgpu_buffer_rsrc_t o = block_rsrc(src.out(r), span);
 #pragma unroll
       for (int t = 0; t < W; ++t) bstore<V>(acc[r][t], o, col, t * pitch);
@@ -189,7 +281,7 @@ __device__ __forceinline__ void code_column(const Src &src, uint32_t col, bool l
 #pragma unroll
     for (int r = 0; r < MO; ++r) {
       if (r >= src.nout()) break;
-      reduce_mod_p<W, N, P, T>(acc[r]);
+      leave_ring<W, N, P, PT, T>(acc[r]);
       if ((uint32_t)(r & 1) != part) {
 #pragma unroll
         for (int t = 0; t < W; ++t) xch[(r * W + t) * 64 + lane] = acc[r][t];
@@ -213,7 +305,7 @@ __device__ __forceinline__ void code_column(const Src &src, uint32_t col, bool l
 // stream: while chunk c's last block is accumulated, chunk c+1's first block
 // is already in flight, so the wave never drains its load pipeline between
 // chunks.
-template <int W, int N, uint32_t P, int MO, int V, class Src>
+template <int W, int N, uint32_t P, int MO, int V, bool PT = false, class Src>
 __device__ __forceinline__ void code_tile(const Src &src, uint32_t col0, uint32_t col1,
                                           uint32_t lane) {
   typedef typename Vec<V>::T T;
@@ -243,15 +335,14 @@ __device__ __forceinline__ void code_tile(const Src &src, uint32_t col0, uint32_
       // next step: block j+1 of this chunk, or block 0 of the next chunk
       const bool last = j + 1 == k;
       prefetch(q ^ 1, last ? cb + kChunk : cb, last ? 0 : j + 1);
-#pragma unroll
-      for (int r = 0; r < MO; ++r) rot_acc<W, N, 0, T>(acc[r], d[q], src.lift(j, r));
+      accumulate<W, N, P, MO, PT, T>(acc, d[q], src.lift4(j));
       if (last) {
         const uint32_t col = cb + lane * 4u * V;
         if (col < S) {
 #pragma unroll
           for (int r = 0; r < MO; ++r) {
             if (r >= src.nout()) break;
-            reduce_mod_p<W, N, P, T>(acc[r]);
+            leave_ring<W, N, P, PT, T>(acc[r]);
             const __amdgpu_buffer_rsrc_t o = block_rsrc(src.out(r), span);
 #pragma unroll
             for (int t = 0; t < W; ++t) bstore<V>(acc[r][t], o, col, t * pitch);

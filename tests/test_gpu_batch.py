@@ -248,3 +248,38 @@ def test_batch_errors():
     empty = P.Batch([])
     empty.launch()
     sync()
+
+
+@pytest.mark.parametrize("mode,split", [("grid", 1), ("grid", 2), ("queue", 1), ("static", 1)])
+def test_parity_and_embedding_stripes_in_one_batch(mode, split):
+    """Parity-transform stripes (encodes and decodes) next to embedding ones
+    in one launch, each against the oracle's definition of its code."""
+    torch = torch_mod()
+    specs = [((4, 5, 0x1F), 4, 2), ((10, 11, 0x7FF), 6, 3), ((6, 9, 0x49), 5, 4), ((8, 17, 0x139), 5, 3)]
+    plans, items, checks = [], [], []
+    keep = []
+    for i, ((w, n, p), k, m) in enumerate(specs * 2):
+        transform = "parity" if (w != 8 and i % 2 == 0) else "embedding"
+        plan = P.Plan(w, n, p, k, m, transform=transform)
+        S = 64 * (40 + 17 * i)
+        rng = np.random.Generator(np.random.PCG64(100 + i))
+        data = [rng.integers(0, 256, w * S, dtype=np.uint8) for _ in range(k)]
+        f = oracle.Field(w, p)
+        if transform == "parity":
+            code = data + oracle.encode_parity_transform(f, n, plan.G, data, S)
+        else:
+            code = data + f.encode(plan.G, data, S)
+        er = [] if i < 4 else [0, k + m - 1]
+        dev = [torch.from_numpy(c.copy()).cuda() for c in code]
+        outs = er if er else list(range(k, k + m))
+        for o in outs:
+            dev[o].fill_(0x99)
+        keep.append((plan, dev))
+        items.append((plan, er, dev, S))
+        checks.append((dev, code, outs))
+    b = P.Batch(items, mode=mode, split_k=split)
+    b.run()
+    sync()
+    for i, (dev, code, outs) in enumerate(checks):
+        for o in outs:
+            assert np.array_equal(to_host(dev[o]), code[o]), (i, o)

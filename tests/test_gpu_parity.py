@@ -424,3 +424,44 @@ def test_sliced_conversion_errors():
     with pytest.raises(P.PyritError) as e:
         P.from_sliced(8, a, b, n_symbols=512, pitch=96)
     assert e.value.code in (-1, -8)
+
+
+# Parity transform (Sec. II-C.1, II-D.1): a different code, checked against
+# the oracle's definition of it.
+PT_RINGS = [(4, 5, 0x1F), (10, 11, 0x7FF), (6, 9, 0x49)]
+
+
+@pytest.mark.parametrize("w,n,p", PT_RINGS)
+@pytest.mark.parametrize("vec", [0, 4, 8, 16])
+def test_parity_transform_encode(w, n, p, vec):
+    k, m = (4, 3) if w == 4 else (7, 4)
+    st = W.Stripe(w, n, p, k=k, m=m, B=RAGGED_S * w - 8, stripe=n + vec, seed=31)
+    plan = P.Plan(w, n, p, k, m, transform="parity")
+    data = [dev_block(st, j) for j in range(k)]
+    par = [dev_empty(st.block_len) for _ in range(m)]
+    plan.encode(data, par, st.S, vec_bytes=vec)
+    sync()
+    host = [W.block_bytes(st.key(j), st.block_len, st.B) for j in range(k)]
+    want = oracle.encode_parity_transform(oracle.Field(w, p), n, plan.G, host, st.S)
+    for i in range(m):
+        assert np.array_equal(to_host(par[i]), want[i]), i
+
+
+@pytest.mark.parametrize("w,n,p", PT_RINGS)
+def test_parity_transform_decode(w, n, p):
+    torch = torch_mod()
+    k, m = (4, 2) if w == 4 else (8, 4)
+    st = W.Stripe(w, n, p, k=k, m=m, B=64 * 96 * w, stripe=7, seed=32)
+    plan = P.Plan(w, n, p, k, m, transform="parity")
+    f = oracle.Field(w, p)
+    host = [W.block_bytes(st.key(j), st.block_len, st.B) for j in range(k)]
+    code = host + oracle.encode_parity_transform(f, n, plan.G, host, st.S)
+    pats = list(itertools.combinations(range(k + m), m))[::max(1, len(list(itertools.combinations(range(k + m), m))) // 25)]
+    for er in pats:
+        dev = [torch.from_numpy(b.copy()).cuda() for b in code]
+        for e in er:
+            dev[e].fill_(0xC3)
+        plan.decode(list(er), dev, st.S)
+        sync()
+        for e in er:
+            assert np.array_equal(to_host(dev[e]), code[e]), (er, e)

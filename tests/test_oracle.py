@@ -366,3 +366,72 @@ def test_sliced_encode_equals_symbolwise_products(w, p):
         for j in range(k):
             want ^= sb.mul(np.full(n, int(C[i, j])), data[j], w, p)
         assert np.array_equal(oracle.from_sliced(w, par[i], n).astype(np.int64), want), i
+
+
+# Parity transform (Sec. II-C.1, II-D.1).
+
+def test_parity_embedding_matches_the_paper_formulas():
+    # AOP, w = 4 and 10: one parity bit on top (b -> (a+b+c+d) x^4 + b)
+    for w, n, p in [(4, 5, 0x1F), (10, 11, 0x7FF)]:
+        t = oracle.parity_embed_table(w, n, p)
+        for b in range(1 << w):
+            assert int(t[b]) == b | ((bin(b).count("1") & 1) << w)
+    # ESP x^6+x^3+1: (a+d) x^6 + (b+e) x^7 + (c+f) x^8
+    t = oracle.parity_embed_table(6, 9, 0x49)
+    for b in range(64):
+        bit = lambda i: (b >> i) & 1
+        want = b | ((bit(0) ^ bit(3)) << 6) | ((bit(1) ^ bit(4)) << 7) | ((bit(2) ^ bit(5)) << 8)
+        assert int(t[b]) == want
+
+
+@pytest.mark.parametrize("w,n,p", [(4, 5, 0x1F), (6, 9, 0x49), (10, 11, 0x7FF)])
+def test_psi_is_a_linear_bijection(w, n, p):
+    psi = oracle.psi_table(w, n, p)
+    assert sorted(psi.tolist()) == list(range(1 << w))
+    rng = np.random.Generator(np.random.PCG64(w))
+    a, b = rng.integers(0, 1 << w, 200), rng.integers(0, 1 << w, 200)
+    assert np.array_equal(psi[a ^ b], psi[a] ^ psi[b])
+
+
+@pytest.mark.parametrize("w,n,p", [(4, 5, 0x1F), (6, 9, 0x49), (10, 11, 0x7FF)])
+def test_parity_transform_code_is_the_literal_ring_computation(w, n, p):
+    """parity_i = drop_high(sum_j C[i][j] * phi_P(d_j)) in R_{2,n}, computed
+    symbol by symbol with the schoolbook ring product (any representative of
+    C[i][j] gives the same product on the ideal, Prop. 2)."""
+    f = oracle.Field(w, p)
+    k, m, S = 3, 2, 8
+    C = f.cauchy(k, m)
+    rng = np.random.Generator(np.random.PCG64(n))
+    data = [rng.integers(0, 256, w * S, dtype=np.uint8) for _ in range(k)]
+    got = oracle.encode_parity_transform(f, n, C, data, S)
+    emb = oracle.parity_embed_table(w, n, p)
+    syms = [oracle.from_sliced(w, d, 8 * S) for d in data]
+    for i in range(m):
+        want = np.zeros(8 * S, dtype=np.int64)
+        for s in range(8 * S):
+            acc = 0
+            for j in range(k):
+                acc ^= sb.ring_mul(int(C[i, j]), int(emb[syms[j][s]]), n)
+            want[s] = acc & ((1 << w) - 1)
+            assert sb.ring_mul(acc, p, n) == 0  # the sum lies in the ideal (h)
+        assert np.array_equal(oracle.from_sliced(w, got[i], 8 * S).astype(np.int64), want), i
+
+
+@pytest.mark.parametrize("w,n,p,k,m", [(4, 5, 0x1F, 4, 2), (6, 9, 0x49, 6, 3)])
+def test_parity_transform_decodes_every_pattern(w, n, p, k, m):
+    f = oracle.Field(w, p)
+    C = f.cauchy(k, m)
+    S = 64
+    rng = np.random.Generator(np.random.PCG64(k))
+    data = [rng.integers(0, 256, w * S, dtype=np.uint8) for _ in range(k)]
+    code = data + oracle.encode_parity_transform(f, n, C, data, S)
+    # not the field code: the parity differs from the embedding code
+    assert not all(np.array_equal(a, b) for a, b in zip(code[k:], f.encode(C, data, S)))
+    for e in range(1, m + 1):
+        for er in itertools.combinations(range(k + m), e):
+            blocks = [c.copy() for c in code]
+            for x in er:
+                blocks[x][:] = 0
+            oracle.decode_parity_transform(f, n, C, list(er), blocks, S)
+            for x in er:
+                assert np.array_equal(blocks[x], code[x]), er

@@ -302,3 +302,22 @@ def test_cauchy_light_decodes_every_pattern_c0_and_c1():
             rec = sb.bitmatrix_encode(D, [code[s] for s in surv], st.w, st.p, S)
             for e, blk in zip(er, rec):
                 assert np.array_equal(blk, code[e]), (st.w, er, e)
+
+
+def test_parity_transform_plans():
+    plan = P.Plan(4, 5, 0x1F, 4, 2, transform="parity")
+    t = ctypes.c_int()
+    assert _lib.lib().pyrit_plan_transform(plan._h, ctypes.byref(t)) == 0 and t.value == 1
+    assert plan.transform == "parity"
+    # same lifted schedule as the embedding plan: only the ring entry/exit differ
+    assert np.array_equal(plan.lifted, P.Plan(4, 5, 0x1F, 4, 2).lifted)
+    G = np.ones((2, 4), dtype=np.uint16)
+    h = ctypes.c_void_p()
+    assert _lib.lib().pyrit_plan_create_ex(4, 5, 0x1F, 4, 2, G.ctypes.data, 2, ctypes.byref(h)) == E["EINVAL"]
+    with pytest.raises(ValueError):
+        P.Plan(4, 5, 0x1F, 4, 2, transform="other")
+    # no parity-transform kernel for the (8,17) ring: plan exists, device calls refuse
+    p8 = P.Plan(8, 17, 0x139, 4, 2, transform="parity")
+    with pytest.raises(P.PyritError) as e:
+        p8.encode([1, 2, 3, 4], [5, 6], 64, stream=0)
+    assert e.value.code == E["EUNSUPPORTED"]
