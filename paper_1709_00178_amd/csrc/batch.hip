@@ -57,9 +57,18 @@ struct BatchArgs {
   uint32_t n_passes;
 };
 
+// Outputs per pass inside the batch kernels: four for every ring.  One kernel
+// holds every ring, and its register count is the largest ring's; four
+// outputs keep each ring near the (8,17) ring's count (about 88 VGPRs, five
+// waves per SIMD), while wider passes would only pay off for codes with more
+// than four parity blocks (the plain kernel takes those in wide passes).
+constexpr int kBatchOut = 4;
+constexpr int batch_max_out(int ring) {
+  return ring_max_out(ring) < kBatchOut ? ring_max_out(ring) : kBatchOut;
+}
+
 // Lane width per ring inside the batch kernels: the widest that keeps every
-// ring at or below the (8,17) ring's register count (about 90 VGPRs with four
-// outputs), so one kernel holds all rings at five waves per SIMD.
+// ring at or below that register count.
 constexpr int kBatchV[kNumRings] = {2, 1, 1, 1, 1, 2, 1, 1};
 
 // kBatchV packed four bits per ring, so a run-time ring id maps to its lane
@@ -90,7 +99,10 @@ struct TableSrc {
   __device__ const uint8_t *in(int j) const { return (const uint8_t *)in_tab[j]; }
   __device__ uint8_t *out(int r) const { return (uint8_t *)out_tab[r]; }
   __device__ uint32_t lift(int j, int r) const { return lift_tab[j * kMaxOut + r]; }
-  __device__ dev::u32x4 lift4(int j) const { return *(const AS4 dev::u32x4 *)(lift_tab + j * kMaxOut); }
+  __device__ dev::Lift8 lift8(int j) const {
+    const AS4 dev::u32x4 *row = (const AS4 dev::u32x4 *)(lift_tab + j * kMaxOut);
+    return dev::Lift8{row[0], row[1]};
+  }
 };
 
 __device__ __forceinline__ TableSrc table_src(const PassDesc &d) {
@@ -122,15 +134,18 @@ template <int RING>
 __device__ __forceinline__ void run_tile(const AS4 PassDesc *pd, uint32_t col0, uint32_t col1,
                                          uint32_t lane) {
   constexpr RingDesc R = kRings[RING];
-  dev::code_tile<R.w, R.n, R.p, kMaxOut, kBatchV[RING], R.parity>(table_src(pd), col0, col1, lane);
+  dev::code_tile<R.w, R.n, R.p, batch_max_out(RING), kBatchV[RING], R.parity>(table_src(pd), col0, col1, lane);
 }
 
-// LDS exchange of the split-K grid kernel, in dwords: kMaxOut outputs x the
-// largest w * V over the rings x 64 lanes.
+// LDS exchange of the split-K grid kernel, in dwords: the largest
+// outputs x w x V over the rings, x 64 lanes.
 constexpr int xch_dwords() {
   int m = 0;
-  for (int i = 0; i < kNumRings; ++i) m = kRings[i].w * kBatchV[i] > m ? kRings[i].w * kBatchV[i] : m;
-  return kMaxOut * m * 64;
+  for (int i = 0; i < kNumRings; ++i) {
+    const int x = batch_max_out(i) * kRings[i].w * kBatchV[i];
+    m = x > m ? x : m;
+  }
+  return m * 64;
 }
 
 template <int RING, int KS>
@@ -141,7 +156,8 @@ __device__ __forceinline__ void run_chunk(const PassDesc &pd, uint32_t base, uin
   typedef typename dev::Vec<V>::T T;
   const TableSrc src = table_src(pd);
   const uint32_t col = base + lane * 4u * V;
-  dev::code_column<R.w, R.n, R.p, kMaxOut, V, KS, R.parity>(src, col, col < src.S(), part, (T *)xch);
+  dev::code_column<R.w, R.n, R.p, batch_max_out(RING), V, KS, R.parity>(src, col, col < src.S(), part,
+                                                                          (T *)xch);
 }
 
 __device__ __forceinline__ void code_item(const AS4 PassDesc *passes, const AS4 WorkItem *it,
@@ -306,7 +322,7 @@ struct HostPass {
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-// Resolve one batch item into passes of at most kMaxOut outputs.
+// Resolve one batch item into passes of at most batch_max_out outputs.
 int item_passes(const pyrit_batch_item &it, std::vector<HostPass> *out, uint64_t *moved) {
   const pyrit_plan *pl = it.plan;
   if (!pl || !it.blocks) return PYRIT_EINVAL;
@@ -337,14 +353,15 @@ int item_passes(const pyrit_batch_item &it, std::vector<HostPass> *out, uint64_t
     if ((uintptr_t)it.blocks[b] & 15u) return PYRIT_EALIGN;
   }
   const int nout = (int)outs.size();
-  for (int r0 = 0; r0 < nout; r0 += kMaxOut) {
+  const int per_pass = batch_max_out(pl->ring);
+  for (int r0 = 0; r0 < nout; r0 += per_pass) {
     HostPass hp;
     hp.k = (uint32_t)pl->k;
     hp.S = (uint32_t)it.slice_bytes;
     hp.pitch = (uint32_t)pitch;
     hp.w = (uint32_t)pl->w;
     hp.ring = pl->ring;
-    hp.nout = (uint32_t)std::min(kMaxOut, nout - r0);
+    hp.nout = (uint32_t)std::min(per_pass, nout - r0);
     for (int b : ins) hp.in.push_back((uint64_t)(uintptr_t)it.blocks[b]);
     for (uint32_t r = 0; r < hp.nout; ++r) hp.out.push_back((uint64_t)(uintptr_t)it.blocks[outs[r0 + r]]);
     hp.lift.assign((size_t)pl->k * kMaxOut, 0);

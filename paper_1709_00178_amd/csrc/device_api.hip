@@ -38,7 +38,7 @@ int launch_pass(int ring, int nout, int vec_bytes, const PassArgs &a, void *stre
 static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
 // Run the passes for `nout` outputs of a lifted k-column matrix L (row r of
-// L belongs to out[r]), at most kMaxOut outputs per pass.
+// L belongs to out[r]), at most ring_max_out outputs per pass.
 static int run_passes(const pyrit_plan *pl, const uint8_t *const *in, uint8_t *const *out, int nout,
                       const uint32_t *L, size_t S, size_t pitch, int vec_bytes, void *stream) {
   PassArgs a;
@@ -51,8 +51,9 @@ static int run_passes(const pyrit_plan *pl, const uint8_t *const *in, uint8_t *c
     if (!aligned16(in[j])) return PYRIT_EALIGN;
     a.in[j] = in[j];
   }
-  for (int r0 = 0; r0 < nout; r0 += kMaxOut) {
-    const int cnt = nout - r0 < kMaxOut ? nout - r0 : kMaxOut;
+  const int per_pass = ring_max_out(pl->ring);
+  for (int r0 = 0; r0 < nout; r0 += per_pass) {
+    const int cnt = nout - r0 < per_pass ? nout - r0 : per_pass;
     for (int r = 0; r < kMaxOut; ++r) a.out[r] = nullptr;
     for (int r = 0; r < cnt; ++r) {
       if (!out[r0 + r]) return PYRIT_EINVAL;

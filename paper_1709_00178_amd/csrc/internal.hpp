@@ -12,8 +12,9 @@
 namespace pyrit {
 
 // Outputs computed by one kernel pass: the accumulators of every output live
-// in registers, so a pass covers at most this many output blocks.
-constexpr int kMaxOut = 4;
+// in registers, so a pass covers at most this many output blocks (the bound
+// of every per-pass array; each ring has its own limit, ring_max_out).
+constexpr int kMaxOut = 8;
 
 // Rings with a device kernel.  The kernels are templates on (w, n, p), so the
 // reduction modulo p and every rotation index are compile-time constants.
@@ -37,6 +38,12 @@ constexpr RingDesc kRings[kNumRings] = {
     {10, 11, 0x7FFu, true},
     {6, 9, 0x49u, true},
 };
+// Outputs per pass of a ring: outputs x n ring slices of accumulators stay
+// near 70 registers per lane (4 for n = 17, 6 for n = 11, 8 for n <= 9).
+constexpr int ring_max_out(int ring) {
+  return kRings[ring].n <= 9 ? 8 : kRings[ring].n <= 11 ? 6 : 4;
+}
+
 // -1 when no kernel exists; transform: PYRIT_TRANSFORM_*
 int ring_id(int w, int n, uint32_t p, int transform = PYRIT_TRANSFORM_EMBEDDING);
 

@@ -1,4 +1,4 @@
-// Plain per-stripe kernel: one launch codes one pass (up to kMaxOut outputs)
+// Plain per-stripe kernel: one launch codes one pass (up to ring_max_out outputs)
 // of one stripe.  Workgroup b is two waves sharing the column chunk of 64
 // lanes x 4V bytes at b * 256V (split-K: each wave codes every other input
 // block; partial sums meet in LDS).
@@ -38,15 +38,20 @@ static int launch_plain_v(int vec_bytes, const PassArgs &a, hipStream_t st) {
   }
 }
 
+template <int RING, int MO>
+static int launch_plain_mo(int nout, int vec_bytes, const PassArgs &a, hipStream_t st) {
+  if constexpr (MO > ring_max_out(RING)) {
+    return PYRIT_EINVAL;
+  } else {
+    if (nout == MO) return launch_plain_v<RING, MO>(vec_bytes, a, st);
+    if constexpr (MO < kMaxOut) return launch_plain_mo<RING, MO + 1>(nout, vec_bytes, a, st);
+    return PYRIT_EINVAL;
+  }
+}
+
 template <int RING>
 int launch_plain_ring(int nout, int vec_bytes, const PassArgs &a, hipStream_t st) {
-  switch (nout) {
-    case 1: return launch_plain_v<RING, 1>(vec_bytes, a, st);
-    case 2: return launch_plain_v<RING, 2>(vec_bytes, a, st);
-    case 3: return launch_plain_v<RING, 3>(vec_bytes, a, st);
-    case 4: return launch_plain_v<RING, 4>(vec_bytes, a, st);
-    default: return PYRIT_EINVAL;
-  }
+  return launch_plain_mo<RING, 1>(nout, vec_bytes, a, st);
 }
 
 }  // namespace pyrit

@@ -27,6 +27,12 @@ namespace dev {
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
+// The lifted coefficients of one input block for up to eight outputs.
+struct Lift8 {
+  u32x4 lo, hi;
+  __device__ __forceinline__ uint32_t operator[](int r) const { return r < 4 ? lo[r] : hi[r - 4]; }
+};
+
 template <int V> struct Vec;
 template <> struct Vec<1> { typedef uint32_t T; };
 template <> struct Vec<2> { typedef u32x2 T; };
@@ -177,7 +183,7 @@ __device__ __forceinline__ void reduce_mod_p(T (&acc)[N]) {
 // transform (the block as is, zero slices implied) or parity transform (the
 // block extended by its parity slices).
 template <int W, int N, uint32_t P, int MO, bool PT, typename T>
-__device__ __forceinline__ void accumulate(T (&acc)[MO][N], const T (&d)[W], const u32x4 &cf) {
+__device__ __forceinline__ void accumulate(T (&acc)[MO][N], const T (&d)[W], const Lift8 &cf) {
   if constexpr (PT) {
     T e[N];
     parity_embed<W, N, P, T>(e, d);
@@ -208,8 +214,8 @@ __device__ __forceinline__ void load_block(typename Vec<V>::T (&d)[W], const uin
 }
 
 // One lane column of one pass.  Src supplies wave-uniform values:
-//   k(), S(), pitch(), nout(), in(j), out(r), lift(j, r) and lift4(j) (the
-//   kMaxOut lifted coefficients of input j in one load); slice t of a block
+//   k(), S(), pitch(), nout(), in(j), out(r), lift(j, r) and lift8(j) (the
+//   kMaxOut lifted coefficients of input j, two 16-byte loads); slice t of a block
 //   starts t * pitch() bytes after its base.  Rows r >= nout() must have
 //   zero lifted coefficients; they are neither reduced nor stored.
 //
@@ -252,7 +258,7 @@ __device__ __forceinline__ void code_column(const Src &src, uint32_t col, bool l
   // load), so no scalar-load wait sits between the vector loads and XORs.
   prefetch(0, (int)part, src.in(clampj((int)part)));
   const uint8_t *ip = src.in(clampj((int)part + KS));
-  u32x4 cf = src.lift4(clampj((int)part));
+  Lift8 cf = src.lift8(clampj((int)part));
   for (int j = (int)part; j < k; j += 2 * KS) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -260,7 +266,7 @@ __device__ __forceinline__ void code_column(const Src &src, uint32_t col, bool l
       if (jq >= k) break;
       prefetch(q ^ 1, jq + KS, ip);
       ip = src.in(clampj(jq + 2 * KS));
-      const u32x4 cn = src.lift4(clampj(jq + KS));
+      const Lift8 cn = src.lift8(clampj(jq + KS));
       accumulate<W, N, P, MO, PT, T>(acc, d[q], cf);
       cf = cn;
     }
@@ -335,7 +341,7 @@ __device__ __forceinline__ void code_tile(const Src &src, uint32_t col0, uint32_
       // next step: block j+1 of this chunk, or block 0 of the next chunk
       const bool last = j + 1 == k;
       prefetch(q ^ 1, last ? cb + kChunk : cb, last ? 0 : j + 1);
-      accumulate<W, N, P, MO, PT, T>(acc, d[q], src.lift4(j));
+      accumulate<W, N, P, MO, PT, T>(acc, d[q], src.lift8(j));
       if (last) {
         const uint32_t col = cb + lane * 4u * V;
         if (col < S) {
@@ -372,7 +378,9 @@ struct KernargSrc {
   __device__ const uint8_t *in(int j) const { return a.in[j]; }
   __device__ uint8_t *out(int r) const { return a.out[r]; }
   __device__ uint32_t lift(int j, int r) const { return a.lift[j][r]; }
-  __device__ u32x4 lift4(int j) const { return *(const u32x4 *)&a.lift[j][0]; }
+  __device__ Lift8 lift8(int j) const {
+    return Lift8{*(const u32x4 *)&a.lift[j][0], *(const u32x4 *)&a.lift[j][4]};
+  }
 };
 
 }  // namespace dev

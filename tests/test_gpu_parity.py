@@ -465,3 +465,36 @@ def test_parity_transform_decode(w, n, p):
         sync()
         for e in er:
             assert np.array_equal(to_host(dev[e]), code[e]), (er, e)
+
+
+# Passes of up to ring_max_out outputs: 8 for n <= 9, 6 for n = 11, 4 for
+# n = 17; m above the limit splits into several passes.
+@pytest.mark.parametrize("w,n,p,k,m,transform", [
+    (4, 5, 0x1F, 8, 8, "embedding"), (4, 5, 0x1F, 7, 9, "parity"),
+    (6, 9, 0x49, 10, 8, "embedding"), (6, 9, 0x49, 11, 17, "parity"),
+    (10, 11, 0x7FF, 10, 6, "embedding"), (10, 11, 0x7FF, 9, 7, "parity"),
+    (8, 17, 0x1D7, 6, 5, "embedding")])
+def test_wide_passes_encode_and_decode(w, n, p, k, m, transform):
+    torch = torch_mod()
+    st = W.Stripe(w, n, p, k=k, m=m, B=64 * 200 * w, stripe=m, seed=41)
+    plan = P.Plan(w, n, p, k, m, transform=transform)
+    f = oracle.Field(w, p)
+    host = [W.block_bytes(st.key(j), st.block_len, st.B) for j in range(k)]
+    if transform == "parity":
+        code = host + oracle.encode_parity_transform(f, n, plan.G, host, st.S)
+    else:
+        code = host + f.encode(plan.G, host, st.S, nthreads=4)
+    dev = [torch.from_numpy(c.copy()).cuda() for c in code]
+    for i in range(m):
+        dev[k + i].fill_(0x11)
+    plan.encode(dev[:k], dev[k:], st.S)
+    sync()
+    for i in range(m):
+        assert np.array_equal(to_host(dev[k + i]), code[k + i]), i
+    er = list(range(0, k + m, max(1, (k + m) // m)))[:m]
+    for e in er:
+        dev[e].fill_(0x22)
+    plan.decode(er, dev, st.S)
+    sync()
+    for e in er:
+        assert np.array_equal(to_host(dev[e]), code[e]), (er, e)
