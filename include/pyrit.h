@@ -13,8 +13,11 @@
  *   - multiplying by x^s rotates slice indices by s modulo n, so a product is
  *     an XOR of rotated slices, and the n ring slices of each output are
  *     reduced modulo p back to w field slices (inverse embedding, Prop. 2).
+ * Plans may instead use the paper's parity transform (Sec. II-C.1 / II-D.1,
+ * see PYRIT_TRANSFORM_PARITY), a different MDS code of the same shape.
  *
- * Data layout.  A block is w contiguous slices of S bytes ("slice_bytes").
+ * Data layout.  A block is w slices of S bytes ("slice_bytes"), contiguous,
+ * or slice_pitch bytes apart in the *_ex calls and in batches.
  * Slice t holds coefficient t of every symbol: symbol (o, b), for byte offset
  * o < S and bit b < 8, is sum_t bit b of byte o of slice t, times x^t.  S must
  * be a positive multiple of 64, every block pointer 16-byte aligned, and
@@ -78,7 +81,9 @@ const char *pyrit_version(void);
  * PYRIT_EINVAL, PYRIT_ENOTIRRED or PYRIT_ENOTDIV. */
 int pyrit_ring_check(int w, int n, uint32_t p);
 
-/* Whether a device kernel exists for this ring (1) or not (0). */
+/* Whether a device kernel exists for this ring with the embedding transform
+ * (1) or not (0).  The parity transform has kernels for (4,5,0x1F),
+ * (10,11,0x7FF) and (6,9,0x49). */
 int pyrit_ring_supported(int w, int n, uint32_t p);
 
 /* Sparse transform of one field element (Sec. II-B): among the 2^(n-w) ring
@@ -174,7 +179,8 @@ int pyrit_decode_matrix(const pyrit_plan *plan, const int *erased, int n_erased,
 /* ------------------------------------------------------------- device calls */
 
 /* Encode: parity[i] = sum_j G[i][j] * data[j] for i < m, computed as
- * rotated-slice XORs in R_{2,n} and reduced mod p.  data: k device pointers,
+ * rotated-slice XORs in R_{2,n} and reduced mod p (for a PARITY plan, the
+ * parity-transform code of PYRIT_TRANSFORM_PARITY).  data: k device pointers,
  * parity: m device pointers (host arrays), each block w * slice_bytes bytes.
  * Outputs must not alias inputs. */
 int pyrit_encode(const pyrit_plan *plan, const uint8_t *const *data, uint8_t *const *parity,
@@ -231,13 +237,14 @@ int pyrit_fill_random(uint8_t *dst, size_t nbytes, size_t nrandom, uint64_t key,
 int pyrit_copy(uint8_t *dst, const uint8_t *src, size_t nbytes, void *stream);
 
 /* ------------------------------------------------------------------ batches
- * Many stripes (any mix of supported rings, k, m, slice sizes, encodes and
- * decodes) coded by ONE persistent kernel launch.  Each stripe is split into
+ * Many stripes (any mix of supported rings and transforms, k, m, slice sizes,
+ * encodes and decodes) coded by ONE kernel launch.  Each stripe is split into
  * passes of at most four outputs and each pass into column tiles; the tiles
- * form a device work queue that resident waves drain.  The launch is a
- * hipGraph with a single kernel node, replayed by pyrit_batch_launch.  The
- * output bytes of every stripe equal those of pyrit_encode / pyrit_decode on
- * the same inputs.
+ * form a work queue that the launch drains (see pyrit_tune.mode).  The launch
+ * is instantiated as a hipGraph with a single kernel node, replayed by
+ * pyrit_batch_launch; pyrit_batch_launch_direct dispatches the same kernel
+ * without the graph.  The output bytes of every stripe equal those of
+ * pyrit_encode / pyrit_decode on the same inputs.
  */
 typedef struct {
   const pyrit_plan *plan;   /* code of this stripe (must outlive the batch) */
