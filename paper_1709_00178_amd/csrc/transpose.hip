@@ -8,10 +8,12 @@
 //
 // One lane handles 32 consecutive symbols: 8 of them fill one byte of every
 // slice, so the lane writes (or reads) one 32-bit word per slice and the 64
-// lanes of a wave cover 256 contiguous bytes of each slice.  The byte-to-slice
-// reshuffle of 8 symbols is an 8 x 8 bit-matrix transpose done with three
-// masked delta swaps on a 64-bit word (an involution, so both directions use
-// it).
+// lanes of a wave cover 256 contiguous bytes of each slice.  The symbol side
+// goes through LDS so that every vector access of a wave covers contiguous
+// bytes (lane i moves 16 bytes at 16 i of each 1 KiB row) while each lane
+// still works on its own 32 symbols.  The byte-to-slice reshuffle of 8
+// symbols is an 8 x 8 bit-matrix transpose done with three masked delta swaps
+// on a 64-bit word (an involution, so both directions use it).
 #include <hip/hip_runtime.h>
 
 #include "internal.hpp"
@@ -35,20 +37,32 @@ __device__ __forceinline__ uint64_t transpose8(uint64_t x) {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-// BYTES = bytes per symbol (1 or 2).  Lane g: symbols 32g .. 32g+31.
+// BYTES = bytes per symbol (1 or 2).  Lane g: symbols 32g .. 32g+31.  The
+// lane count is a multiple of 16, so the last wave may be partial: 16-byte
+// units owned by lanes past the end are neither loaded nor stored.
 template <int BYTES>
 __global__ __launch_bounds__(kTransposeWG) void to_sliced_kernel(const uint8_t *sym, uint8_t *out,
                                                                    uint32_t w, uint32_t pitch,
                                                                    uint32_t lanes) {
+  __shared__ u32x4 stage[kTransposeWG / 64][2 * BYTES][64];
   const uint32_t g = blockIdx.x * kTransposeWG + threadIdx.x;
+  const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+  const uint32_t g0 = g - lane;  // first lane of this wave
+  // coalesced: row i of the wave's 32 * 64 * BYTES bytes is lane-contiguous
+  const u32x4 *src = (const u32x4 *)(sym + (size_t)g0 * 32 * BYTES);
+#pragma unroll
+  for (int i = 0; i < 2 * BYTES; ++i) {
+    const uint32_t e = i * 64 + lane;  // 16-byte unit of the wave's span
+    if (g0 + e / (2 * BYTES) < lanes) stage[wv][e % (2 * BYTES)][e / (2 * BYTES)] = __builtin_nontemporal_load(src + e);
+  }
+  __syncthreads();
   if (g >= lanes) return;
   // 32 symbols = 32 * BYTES bytes as 64-bit words: word q holds symbols
   // 8q/BYTES ..; for BYTES = 2, byte 2i is the low half of symbol i.
   uint64_t v[4 * BYTES];
-  const u32x4 *src = (const u32x4 *)(sym + (size_t)g * 32 * BYTES);
 #pragma unroll
   for (int i = 0; i < 2 * BYTES; ++i) {
-    const u32x4 x = __builtin_nontemporal_load(src + i);
+    const u32x4 x = stage[wv][i][lane];
     v[2 * i] = ((uint64_t)x.y << 32) | x.x;
     v[2 * i + 1] = ((uint64_t)x.w << 32) | x.z;
   }
@@ -76,7 +90,9 @@ __global__ __launch_bounds__(kTransposeWG) void to_sliced_kernel(const uint8_t *
   }
   // slice t word = byte t of lo[0..3] (or byte t-8 of hi[0..3])
   uint8_t *dst = out + (size_t)g * 4;
-  for (uint32_t t = 0; t < w; ++t) {
+#pragma unroll
+  for (int t = 0; t < 8 * BYTES; ++t) {
+    if ((uint32_t)t >= w) break;
     uint32_t word = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -91,15 +107,25 @@ template <int BYTES>
 __global__ __launch_bounds__(kTransposeWG) void from_sliced_kernel(const uint8_t *in, uint8_t *sym,
                                                                      uint32_t w, uint32_t pitch,
                                                                      uint32_t lanes) {
+  __shared__ u32x4 stage[kTransposeWG / 64][2 * BYTES][64];
   const uint32_t g = blockIdx.x * kTransposeWG + threadIdx.x;
-  if (g >= lanes) return;
+  const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+  const uint32_t g0 = g - lane;
+  const bool live = g < lanes;
   uint64_t lo[4] = {0, 0, 0, 0}, hi[4] = {0, 0, 0, 0};
   const uint8_t *src = in + (size_t)g * 4;
-  for (uint32_t t = 0; t < w; ++t) {
-    const uint32_t word = __builtin_nontemporal_load((const uint32_t *)(src + (size_t)t * pitch));
+  // all slice words in flight before any is used
+  uint32_t words[8 * BYTES];
+#pragma unroll
+  for (int t = 0; t < 8 * BYTES; ++t)
+    words[t] = (live && (uint32_t)t < w)
+                   ? __builtin_nontemporal_load((const uint32_t *)(src + (size_t)t * pitch))
+                   : 0u;
+#pragma unroll
+  for (int t = 0; t < 8 * BYTES; ++t) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const uint64_t b = (word >> (8 * q)) & 0xFFu;
+      const uint64_t b = (words[t] >> (8 * q)) & 0xFFu;
       if (t < 8)
         lo[q] |= b << (8 * t);
       else
@@ -126,7 +152,6 @@ __global__ __launch_bounds__(kTransposeWG) void from_sliced_kernel(const uint8_t
       v[2 * q + 1] = b;
     }
   }
-  u32x4 *dst = (u32x4 *)(sym + (size_t)g * 32 * BYTES);
 #pragma unroll
   for (int i = 0; i < 2 * BYTES; ++i) {
     u32x4 x;
@@ -134,7 +159,15 @@ __global__ __launch_bounds__(kTransposeWG) void from_sliced_kernel(const uint8_t
     x.y = (uint32_t)(v[2 * i] >> 32);
     x.z = (uint32_t)v[2 * i + 1];
     x.w = (uint32_t)(v[2 * i + 1] >> 32);
-    dst[i] = x;
+    stage[wv][i][lane] = x;
+  }
+  __syncthreads();
+  // coalesced: 16-byte unit e of the wave's span belongs to lane e / (2 BYTES)
+  u32x4 *dst = (u32x4 *)(sym + (size_t)g0 * 32 * BYTES);
+#pragma unroll
+  for (int i = 0; i < 2 * BYTES; ++i) {
+    const uint32_t e = i * 64 + lane;
+    if (g0 + e / (2 * BYTES) < lanes) dst[e] = stage[wv][e % (2 * BYTES)][e / (2 * BYTES)];
   }
 }
 
