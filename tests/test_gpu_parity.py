@@ -498,3 +498,38 @@ def test_wide_passes_encode_and_decode(w, n, p, k, m, transform):
     sync()
     for e in er:
         assert np.array_equal(to_host(dev[e]), code[e]), (er, e)
+
+
+def test_one_plan_on_concurrent_streams():
+    """One plan coding on four streams at once: each stream encodes its own
+    copy of the data and decodes its own erasure pattern (the decode cache
+    fills from several host calls in flight)."""
+    torch = torch_mod()
+    st = W.Stripe(8, 17, 0x139, k=10, m=4, B=64 * 512 * 8, seed=61)
+    plan = P.Plan(st.w, st.n, st.p, st.k, st.m)
+    f = oracle.Field(st.w, st.p)
+    host = [W.block_bytes(st.key(j), st.block_len, st.B) for j in range(st.k)]
+    code = host + f.encode(plan.G, host, st.S, nthreads=4)
+    pats = [[0, 3, 11], [1, 2, 12, 13], [4], [5, 6, 7, 8]]
+    sets = []
+    for er in pats:
+        data = [torch.from_numpy(h.copy()).cuda() for h in host]
+        par = [dev_empty(st.block_len) for _ in range(st.m)]
+        word = [torch.from_numpy(c.copy()).cuda() for c in code]
+        sets.append((torch.cuda.Stream(), er, data, par, word))
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for s, er, data, par, word in sets:
+            with torch.cuda.stream(s):
+                for e in er:
+                    word[e].fill_(rep + 1)
+                for t in par:
+                    t.fill_(rep + 1)
+            plan.encode(data, par, st.S, stream=s)
+            plan.decode(er, word, st.S, stream=s)
+        torch.cuda.synchronize()
+        for s, er, data, par, word in sets:
+            for i in range(st.m):
+                assert np.array_equal(to_host(par[i]), code[st.k + i]), (rep, er, i)
+            for e in er:
+                assert np.array_equal(to_host(word[e]), code[e]), (rep, er, e)

@@ -321,3 +321,27 @@ def test_parity_transform_plans():
     with pytest.raises(P.PyritError) as e:
         p8.encode([1, 2, 3, 4], [5, 6], 64, stream=0)
     assert e.value.code == E["EUNSUPPORTED"]
+
+
+def test_decode_matrix_cache_under_threads():
+    """Many threads ask one plan for decoding matrices at once (ctypes drops
+    the GIL in the call): every answer equals the single-threaded one."""
+    import concurrent.futures as cf
+    st = W.c1()
+    plan = P.Plan(st.w, st.n, st.p, st.k, st.m)
+    pats = list(itertools.combinations(range(14), 4))[:120]
+    ref = {er: plan.decode_matrix(list(er)) for er in pats[:40]}
+    fresh = P.Plan(st.w, st.n, st.p, st.k, st.m)
+
+    def work(i):
+        er = pats[(i * 7) % len(pats)]
+        surv, D = fresh.decode_matrix(list(er))
+        return er, surv, D
+
+    with cf.ThreadPoolExecutor(8) as ex:
+        res = list(ex.map(work, range(400)))
+    for er, surv, D in res:
+        s2, D2 = plan.decode_matrix(list(er))
+        assert list(surv) == list(s2) and np.array_equal(D, D2), er
+    for er, (s, D) in ref.items():
+        assert np.array_equal(D, fresh.decode_matrix(list(er))[1])
