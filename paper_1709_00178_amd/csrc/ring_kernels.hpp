@@ -76,12 +76,23 @@ __device__ __forceinline__ typename Vec<V>::T bload(__amdgpu_buffer_rsrc_t r, ui
 template <int V>
 __device__ __forceinline__ void bstore(typename Vec<V>::T x, __amdgpu_buffer_rsrc_t r,
                                        uint32_t voff, uint32_t soff) {
-  if constexpr (V == 1)
+  if constexpr (V == 1) {
     __builtin_amdgcn_raw_buffer_store_b32(x, r, voff, soff, kStorePolicy);
-  else if constexpr (V == 2)
+  } else if constexpr (V == 2) {
     __builtin_amdgcn_raw_buffer_store_b64(x, r, voff, soff, kStorePolicy);
-  else
-    __builtin_amdgcn_raw_buffer_store_b128(x, r, voff, soff, kStorePolicy);
+  } else {
+    // Two 8-byte stores, not one 16-byte store: a store of more than 64 bits
+    // reads its data registers after issue, and the compiler has been seen
+    // to let the next instruction overwrite them with no wait state between
+    // (a VALU write right after buffer_store_dwordx4, on gfx950), which
+    // corrupts the stored data now and then.
+    // (The empty asm keeps the two halves from being merged back into one
+    // 16-byte store.)
+    const u32x2 lo = {x.x, x.y}, hi = {x.z, x.w};
+    __builtin_amdgcn_raw_buffer_store_b64(lo, r, voff, soff, kStorePolicy);
+    __asm__ volatile("" ::: "memory");
+    __builtin_amdgcn_raw_buffer_store_b64(hi, r, voff + 8u, soff, kStorePolicy);
+  }
 }
 
 // ---- parity transform (Sec. II-C.1, II-D.1), all at compile time --------

@@ -165,3 +165,60 @@ def test_pool_too_small_is_an_error():
     with pytest.raises(P.PyritError) as e:
         sv.run(prep.array)
     assert e.value.code == -12
+
+
+def test_c4_full_rate_first_100ms():
+    """The served mix at its full configuration (Poisson 20k req/s, 5% C1-shaped
+    64 MiB-block requests, 4 slots, 64 GiB pool), first 0.1 s of the trace:
+    every request's outputs equal the plain kernel's on the same inputs
+    (compared on the device), and sampled columns of every 20th request equal
+    the oracle's."""
+    import ctypes
+    torch = torch_mod()
+    trace = [r for r in W.c4() if r.arrival_s < 0.1]
+    assert any(r.large for r in trace) and len(trace) > 1500
+    inputs = serve.InputPool(16 << 30, key=W.BASE_SEED + 4)
+    plans = {}
+    prep = serve.prepare(trace, inputs, plans)
+    sv = serve.Server(pool_bytes=64 << 30, slots=4, release_outputs=False, block_skew=4352)
+    res, stats = sv.run(prep.array)
+    assert (res["done_s"] > 0).all() and stats["launches"] <= len(trace)
+    lib = P._lib.lib()
+    f_cache = {}
+    for i, (st, offs, large) in enumerate(prep.meta):
+        plan = plans[(st.w, st.n, st.p, st.k, st.m)]
+        blocks = [None] * (st.k + st.m)
+        er = set(st.erased)
+        ins = [b for b in range(st.k + st.m) if b not in er][:st.k] if st.erased else list(range(st.k))
+        for b, o in zip(ins, offs):
+            blocks[b] = inputs.buf[o:o + st.block_len]
+        outs = list(st.erased) if st.erased else list(range(st.k, st.k + st.m))
+        for b in outs:
+            blocks[b] = torch.empty(st.block_len, dtype=torch.uint8, device="cuda")
+        if st.erased:
+            plan.decode(list(st.erased), blocks, st.S)
+        else:
+            plan.encode(blocks[:st.k], blocks[st.k:], st.S)
+        for q, b in enumerate(outs):
+            mixed = torch.empty(st.block_len, dtype=torch.uint8, device="cuda")
+            src = sv.pool_base + int(res[i]["out_offset"] + q * res[i]["out_stride"])
+            assert lib.pyrit_copy(ctypes.c_void_p(mixed.data_ptr()), ctypes.c_void_p(src),
+                                  st.block_len // 16 * 16, None) == 0
+            assert torch.equal(mixed[:st.block_len // 16 * 16], blocks[b][:st.block_len // 16 * 16]), (i, q)
+        if i % 20 == 0:
+            cols = sample_cols(st.S, 6, i)
+            f = f_cache.setdefault((st.w, st.p), oracle.Field(st.w, st.p))
+            G = plan.decode_matrix(list(st.erased))[1] if st.erased else plan.G
+            mini = []
+            for o in offs:
+                idx = (o + np.arange(st.w)[:, None] * st.S + cols[None, :]).reshape(-1)
+                mini.append(inputs.buf[torch.as_tensor(idx, device="cuda")].cpu().numpy())
+            want = f.encode(G, mini, len(cols))
+            for q, b in enumerate(outs):
+                idx = torch.as_tensor((np.arange(st.w)[:, None] * st.S + cols[None, :]).reshape(-1),
+                                      device="cuda")
+                assert np.array_equal(blocks[b][idx].cpu().numpy(), want[q]), (i, q)
+        del blocks
+    sv.close()
+    del inputs
+    torch.cuda.empty_cache()
