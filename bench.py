@@ -297,6 +297,27 @@ def bench_c1(args, stream, out, log):
                                  "plain_GBps_moved": round(moved / (lp_ms * 1e-3) / 1e9, 1),
                                  "batched_GBps_moved": round(moved / (lb_ms * 1e-3) / 1e9, 1)}
     del lbatch
+    # two resident C1 stripes encoded in turn: each launch now finds few of
+    # its address translations cached, since the two stripes together
+    # (1.9 GB) exceed what the per-CU translation caches hold
+    st2 = dataclasses.replace(st, stripe=1)
+    arena2 = Arena(arena_bytes([st2], BLOCK_SKEW), BLOCK_SKEW)
+    blocks2 = stripe_buffers(st2, arena2)
+    batch2 = P.Batch([(plan, [], blocks2, st2.S, st2.pitch)], **res["batched"]["executor"])
+
+    def alternate():
+        batch.run(stream)
+        batch2.run(stream)
+
+    for _ in range(3):
+        alternate()
+    alt_ms = min(batch_time_ms(alternate, 10, stream) for _ in range(3)) / 2
+    out["c1"]["two_stripes_alternating"] = {
+        "GBps_data": round(st.k * st.B / (alt_ms * 1e-3) / 1e9, 1),
+        "GBps_moved": round(moved / (alt_ms * 1e-3) / 1e9, 1),
+        "frac_of_peak": round(moved / (alt_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+        "avg_launch_ms": round(alt_ms, 4)}
+    del batch2, arena2, blocks2
     del batch, dbatch, arena, blocks
     torch.cuda.empty_cache()
 
