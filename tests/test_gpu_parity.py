@@ -355,6 +355,50 @@ def test_slice_pitch_plain_and_batched(w, n, p, pad):
     del torch
 
 
+def test_largest_block_the_abi_accepts():
+    """A block whose slices reach the end of the 31-bit slice window: S just
+    under 256 MiB at a pitch of S + 64, so (w - 1) * pitch + S = 2^31 - 64.
+    Plain and batched encodes and a decode, checked on sampled columns (the
+    last byte of the last slice included); one more 64 bytes of pitch is
+    refused before anything runs."""
+    torch = torch_mod()
+    w, n, p, k, m = 8, 17, 0x139, 2, 1
+    S = (1 << 28) - 64
+    st = W.Stripe(w, n, p, k=k, m=m, B=w * S, seed=41, pad=64)
+    assert st.S == S and (w - 1) * st.pitch + S == (1 << 31) - 64
+    plan = P.Plan(w, n, p, k, m)
+    data = [dev_block(st, j) for j in range(k)]
+    cols = sample_cols(S, 512, 6)
+    want = oracle_cols(st, plan.G, range(k), cols)
+    idx = torch.from_numpy((np.arange(w)[:, None] * st.pitch + cols[None, :]).reshape(-1)).cuda()
+
+    def at_cols(t):
+        return t[idx].cpu().numpy()
+
+    par = dev_empty(st.block_len)
+    for path in ["plain", "grid"]:
+        par.fill_(0x5A)
+        if path == "plain":
+            plan.encode(data, [par], S, pitch=st.pitch)
+        else:
+            P.Batch([(plan, [], data + [par], S, st.pitch)], mode="grid", wg_threads=128,
+                    split_k=2).launch_direct()
+        sync()
+        assert np.array_equal(at_cols(par), want[0]), path
+    lost = data[0].clone()
+    data[0].fill_(0)
+    plan.decode([0], [data[0], data[1], par], S, pitch=st.pitch)
+    sync()
+    assert np.array_equal(at_cols(data[0]), gen_cols(st, 0, cols))
+    for t in range(w):
+        sl = slice(t * st.pitch, t * st.pitch + S)
+        assert torch.equal(data[0][sl], lost[sl]), t
+    with pytest.raises(P.PyritError) as e:
+        plan.encode(data, [par], S, pitch=st.pitch + 64)
+    assert e.value.code == -1
+    del torch
+
+
 # Symbol-major <-> bit-sliced conversions on the device against the oracle's.
 # 512 * 257 symbols: 4112 lanes, not a multiple of the 256-lane workgroup.
 N_SYM = 512 * 257
