@@ -55,6 +55,8 @@ struct BatchArgs {
   uint32_t n_items;
   uint32_t total_waves;
   uint32_t n_passes;
+  // grid mode with XCD order: XCD x codes items [xcd_start[x], xcd_start[x+1])
+  uint32_t xcd_start[kXcds + 1];
 };
 
 // Outputs per pass inside the batch kernels: four for every ring.  One kernel
@@ -184,7 +186,10 @@ __device__ __forceinline__ void code_item(const AS4 PassDesc *passes, const AS4 
 //
 // The dispatcher deals workgroups round-robin over the XCDs (workgroup i to
 // XCD i mod 8).  With XCD_ORDER the workgroup-to-item map is permuted so that
-// each XCD walks its own contiguous eighth of the queue.
+// each XCD walks its own contiguous range of the queue.  The host cuts the
+// queue into eight ranges of equal bytes moved (items of different codes
+// differ up to 10x in cost), and the grid holds eight times the longest
+// range: workgroups past the end of their XCD's range leave at once.
 //
 // KS = 2 (split-K, 128-thread workgroups only): the two waves share one
 // chunk, each coding every other input block (see code_column).
@@ -198,8 +203,9 @@ __global__ __launch_bounds__(WG) void batch_grid_kernel(const BatchArgs a) {
   uint32_t b = blockIdx.x;
   if constexpr (XCD_ORDER) {
     const uint32_t x = b % kXcds, i = b / kXcds;
-    const uint32_t per = gridDim.x / kXcds, rem = gridDim.x % kXcds;
-    b = x < rem ? x * (per + 1u) + i : rem * (per + 1u) + (x - rem) * per + i;
+    const uint32_t first = a.xcd_start[x];
+    if (i >= a.xcd_start[x + 1] - first) return;
+    b = first + i;
   }
   uint32_t lo = 0, hi = a.n_passes;
   while (hi - lo > 1) {
@@ -498,6 +504,27 @@ int build_batch_image(const pyrit_batch_item *items, int n_items, const pyrit_tu
     starts.assign(passes.size() + 1, (uint32_t)work.size());
     for (size_t i = work.size(); i-- > 0;) starts[work[i].pass] = (uint32_t)i;
   }
+  // grid mode with XCD order: eight contiguous ranges of equal bytes moved
+  bi->xcd_start.assign(kXcds + 1, (uint32_t)work.size());
+  bi->xcd_start[0] = 0;
+  uint32_t longest = 0;
+  if (!persistent && t.xcd_order) {
+    auto cost = [&](const WorkItem &it) {
+      const HostPass &hp = passes[it.pass];
+      const uint64_t c1 = std::min<uint64_t>(it.col1, hp.S);
+      return (uint64_t)(hp.k + hp.nout) * hp.w * (c1 > it.col0 ? c1 - it.col0 : 0);
+    };
+    uint64_t total = 0;
+    for (const WorkItem &it : work) total += cost(it);
+    uint64_t acc = 0;
+    uint32_t x = 1;
+    for (size_t i = 0; i < work.size(); ++i) {
+      while (x < kXcds && acc * kXcds >= total * x) bi->xcd_start[x++] = (uint32_t)i;
+      acc += cost(work[i]);
+    }
+    for (uint32_t y = 0; y < kXcds; ++y)
+      longest = std::max(longest, bi->xcd_start[y + 1] - bi->xcd_start[y]);
+  }
 
   // Image: counters | starts | passes | items | pointer and lift tables.
   bi->off_start = (size_t)kGroups * 64;
@@ -541,7 +568,7 @@ int build_batch_image(const pyrit_batch_item *items, int n_items, const pyrit_tu
   bi->wg = t.wg_threads;
   bi->xcd_order = t.xcd_order;
   bi->split = t.split_k;
-  bi->grid = persistent ? grid : (int)work.size();
+  bi->grid = persistent ? grid : t.xcd_order ? (int)(kXcds * longest) : (int)work.size();
   return PYRIT_OK;
 }
 
@@ -554,6 +581,7 @@ static BatchArgs image_args(const BatchImage &bi, void *dev) {
   a.n_items = bi.n_items;
   a.total_waves = bi.total_waves;
   a.n_passes = bi.n_passes;
+  for (uint32_t x = 0; x <= kXcds; ++x) a.xcd_start[x] = bi.xcd_start[x];
   return a;
 }
 

@@ -105,6 +105,7 @@ struct BatchImage {
   uint32_t n_items = 0, n_passes = 0, total_waves = 0;
   int grid = 0, wg = 128, mode = 0, xcd_order = 0, split = 1;
   uint64_t moved = 0;
+  std::vector<uint32_t> xcd_start;  // grid mode with XCD order: per-XCD item ranges
 };
 int batch_check_tune(pyrit_tune *t);
 int batch_resident_grid(const pyrit_tune &t, int *grid);
