@@ -469,37 +469,61 @@ def bench_c2(args, stream, out, log):
 
 
 def bench_c3(args, stream, out, log):
+    """4096 uneven stripes (30% decodes) in one autotuned batch launch, with
+    every slice starting at a 256-byte boundary (slice pitch = S rounded up
+    to 256; the gap is never touched), and in the packed layout (pitch = S,
+    slices only 64-byte aligned)."""
+    import dataclasses
+
     import torch
 
     import paper_1709_00178_amd as P
     from paper_1709_00178_amd import autotune
     from paper_1709_00178_amd import workloads as W
-    stripes = W.c3()
+    base = W.c3()
     plans = {}
-    for st in stripes:
+    for st in base:
         key = (st.w, st.n, st.p, st.k, st.m)
         if key not in plans:
             plans[key] = P.Plan(*key)
-    arena = Arena(arena_bytes(stripes, BLOCK_SKEW), BLOCK_SKEW)
-    bl = [stripe_buffers(st, arena) for st in stripes]
-    items = [(plans[(st.w, st.n, st.p, st.k, st.m)], list(st.erased), b, st.S)
-             for st, b in zip(stripes, bl)]
-    batch, cfg, _ = autotune.tuned_batch(items, stream, log=log)
-    t0 = time.perf_counter()
-    P.Batch(items, **cfg).close()
-    build_s = time.perf_counter() - t0
-    torch.cuda.synchronize()
-    batch.run(stream)
-    b_ms = batch_time_ms(lambda: batch.run(stream), 10, stream)
-    moved = batch.info()["moved_bytes"]
-    out["c3"] = {"stripes": len(stripes), "decodes": sum(1 for s in stripes if s.erased),
-                 "moved_GB": round(moved / 1e9, 3), "ms": round(b_ms, 3),
-                 "GBps_moved": round(moved / (b_ms * 1e-3) / 1e9, 1),
-                 "frac_of_peak": round(moved / (b_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
-                 "batch_build_s": round(build_s, 3), "executor": cfg,
-                 "work_items": batch.info()["work_items"]}
-    del batch, arena, bl
-    torch.cuda.empty_cache()
+    res = {}
+    for name, align in (("pitch_256", 256), ("packed", 0)):
+        if align:
+            stripes = [dataclasses.replace(st, pad=-(-st.S // align) * align - st.S) for st in base]
+        else:
+            stripes = base
+        arena = Arena(arena_bytes(stripes, BLOCK_SKEW), BLOCK_SKEW)
+        bl = []
+        for st in stripes:
+            ins = list(W.survivors(st))
+            outs = list(st.erased) if st.erased else list(range(st.k, st.k + st.m))
+            blocks = [None] * (st.k + st.m)
+            for b in ins + outs:
+                blocks[b] = arena.take(st.block_len)
+            for b in ins:
+                # padded blocks: generator bytes over the whole block memory
+                P.fill_random(blocks[b], st.key(b), nrandom=st.B if not st.pad else st.block_len)
+            bl.append(blocks)
+        items = [(plans[(st.w, st.n, st.p, st.k, st.m)], list(st.erased), b, st.S, st.pitch)
+                 for st, b in zip(stripes, bl)]
+        batch, cfg, _ = autotune.tuned_batch(items, stream, log=log)
+        t0 = time.perf_counter()
+        P.Batch(items, **cfg).close()
+        build_s = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        batch.run(stream)
+        b_ms = batch_time_ms(lambda: batch.run(stream), 10, stream)
+        moved = batch.info()["moved_bytes"]
+        res[name] = {"ms": round(b_ms, 3), "GBps_moved": round(moved / (b_ms * 1e-3) / 1e9, 1),
+                     "frac_of_peak": round(moved / (b_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                     "batch_build_s": round(build_s, 3), "executor": cfg,
+                     "work_items": batch.info()["work_items"]}
+        del batch, arena, bl, items
+        torch.cuda.empty_cache()
+    out["c3"] = dict({"stripes": len(base), "decodes": sum(1 for s in base if s.erased),
+                      "moved_GB": round(moved / 1e9, 3), "layout": "pitch_256"},
+                     **res["pitch_256"])
+    out["c3"]["packed_layout"] = res["packed"]
 
 
 def bench_c4(args, stream, out, log):
@@ -515,7 +539,7 @@ def bench_c4(args, stream, out, log):
     for key, rate, dur in [("c4", 20000.0, 2.0), ("c4_stress_80k", 80000.0, 1.0)]:
         trace = W.c4(rate=rate, duration_s=dur)
         t0 = time.perf_counter()
-        prep = serve.prepare(trace, inputs, plans)
+        prep = serve.prepare(trace, inputs, plans, pitch_align=256)
         prep_s = time.perf_counter() - t0
         offered = sum(r.stripe.k * r.stripe.B for r in trace) / dur
         res = {"rate_per_s": rate, "duration_s": dur, "requests": len(trace),

@@ -66,23 +66,26 @@ def _save_file(d: dict) -> None:
 
 def signature(items) -> str:
     """Batch class: rings present, k/outputs ranges, log2 slice size range,
-    decode share and stripe-count class."""
-    rings, ks, outs, sizes, dec = set(), [], [], [], 0
+    decode share, stripe-count class and the slice alignment (the largest
+    power of two up to 4096 dividing every slice pitch)."""
+    rings, ks, outs, sizes, dec, align = set(), [], [], [], 0, 4096
     for it in items:
         plan, erased, _, S = it[:4]
+        pitch = it[4] if len(it) > 4 and it[4] else S
         rings.add((plan.w, plan.n, plan.p))
         ks.append(plan.k)
         outs.append(len(erased) if erased else plan.m)
         sizes.append(S)
         dec += 1 if erased else 0
+        align = min(align, pitch & -pitch)
     n = len(ks)
     if n == 0:
         return "empty"
     return "|".join([
-        "v3", ",".join(f"{w}/{nn}/{p:x}" for w, nn, p in sorted(rings)),
+        "v4", ",".join(f"{w}/{nn}/{p:x}" for w, nn, p in sorted(rings)),
         f"k{min(ks)}-{max(ks)}", f"o{min(outs)}-{max(outs)}",
         f"s{int(math.log2(min(sizes)))}-{int(math.log2(max(sizes)))}",
-        f"d{round(10 * dec / n)}", f"n{int(math.log2(n))}",
+        f"d{round(10 * dec / n)}", f"n{int(math.log2(n))}", f"a{align}",
     ])
 
 

@@ -10,6 +10,7 @@ pool, whose size caps the working set.
 from __future__ import annotations
 
 import ctypes
+import dataclasses
 
 import numpy as np
 
@@ -92,14 +93,18 @@ class Prepared:
         return len(self.meta)
 
 
-def prepare(trace, inputs: InputPool, plans: dict) -> Prepared:
+def prepare(trace, inputs: InputPool, plans: dict, pitch_align: int = 0) -> Prepared:
     """trace: workload Requests (arrival_s, stripe, large).  plans: dict keyed
-    by (w, n, p, k, m) (filled as needed).  Inputs are packed blocks."""
+    by (w, n, p, k, m) (filled as needed).  Blocks are packed (slice pitch =
+    S) when ``pitch_align`` is 0; else each slice starts at the next multiple
+    of ``pitch_align`` bytes (the stripes in ``meta`` then carry that padding)."""
     n = len(trace)
     arr = (Request * max(1, n))()
     keep, meta = [], []
     for i, rq in enumerate(trace):
         st = rq.stripe
+        if pitch_align:
+            st = dataclasses.replace(st, pad=-(-st.S // pitch_align) * pitch_align - st.S)
         key = (st.w, st.n, st.p, st.k, st.m)
         if key not in plans:
             plans[key] = Plan(*key)
@@ -114,7 +119,7 @@ def prepare(trace, inputs: InputPool, plans: dict) -> Prepared:
         arr[i].erased = ctypes.cast(er, ctypes.POINTER(ctypes.c_int))
         arr[i].inputs = ctypes.cast(ins, ctypes.POINTER(ctypes.c_void_p))
         arr[i].slice_bytes = st.S
-        arr[i].slice_pitch = 0
+        arr[i].slice_pitch = st.pitch
         meta.append((st, offs, rq.large))
     return Prepared(arr, keep + [plans], meta)
 

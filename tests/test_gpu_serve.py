@@ -67,9 +67,9 @@ def _alone(plan, st, inputs, offs):
     for b in outs:
         blocks[b] = torch.empty(st.block_len, dtype=torch.uint8, device="cuda")
     if st.erased:
-        plan.decode(list(st.erased), blocks, st.S)
+        plan.decode(list(st.erased), blocks, st.S, pitch=st.pitch)
     else:
-        plan.encode(blocks[:st.k], blocks[st.k:], st.S)
+        plan.encode(blocks[:st.k], blocks[st.k:], st.S, pitch=st.pitch)
     torch.cuda.synchronize()
     return [blocks[b].cpu().numpy() for b in outs], ins
 
@@ -114,6 +114,30 @@ def test_served_mix_equals_alone_and_oracle():
                 assert np.array_equal(got, want[q]), (i, q)
     sv.close()
     del torch
+
+
+def test_served_mix_with_256_byte_aligned_slices():
+    """Requests whose slices start at 256-byte boundaries (slice pitch = S
+    rounded up to 256, as the benchmark serves them): every coded slice equals
+    the same request coded alone at that pitch."""
+    trace = small_trace(n=120, seed=13)
+    inputs = serve.InputPool(256 << 20, key=0xA11CE)
+    plans = {}
+    prep = serve.prepare(trace, inputs, plans, pitch_align=256)
+    assert all(st.pitch % 256 == 0 and st.S <= st.pitch < st.S + 256 for st, _, _ in prep.meta)
+    assert sum(st.pitch != st.S for st, _, _ in prep.meta) > len(trace) // 2
+    sv = serve.Server(pool_bytes=2 << 30, slots=3, release_outputs=False)
+    res, stats = sv.run(prep.array)
+    assert stats["launches"] < len(trace)
+    for i, (st, offs, large) in enumerate(prep.meta):
+        plan = plans[(st.w, st.n, st.p, st.k, st.m)]
+        alone, _ = _alone(plan, st, inputs, offs)
+        for q, blk in enumerate(alone):
+            mixed = _pool_view(sv, int(res[i]["out_offset"] + q * res[i]["out_stride"]), st.block_len)
+            for t in range(st.w):
+                sl = slice(t * st.pitch, t * st.pitch + st.S)
+                assert np.array_equal(mixed[sl], blk[sl]), (i, q, t, st)
+    sv.close()
 
 
 def test_per_request_mode_same_bytes():
