@@ -201,9 +201,9 @@ int pyrit_decode(const pyrit_plan *plan, const int *erased, int n_erased,
  *     a large power of two keeps the slices of a block off the same HBM
  *     channel and bank (measured on MI355X: 8 MiB slices at a pitch of
  *     8 MiB + 4 KiB stream 8% faster than packed).  Slices that start on
- *     256-byte boundaries (block 256-byte aligned, P a multiple of 256) keep
- *     every wave access within whole cache lines: a batch of mixed slice
- *     sizes measured 5% faster than with 64-byte aligned packed slices.
+ *     128-byte boundaries (block and P multiples of 128) keep every wave
+ *     access within whole 128-byte cache lines: a batch of mixed slice sizes
+ *     measured 5% faster than with 64-byte aligned packed slices.
  *   vec_bytes: column bytes per lane (4, 8 or 16; 0 = library choice). */
 int pyrit_encode_ex(const pyrit_plan *plan, const uint8_t *const *data, uint8_t *const *parity,
                     size_t slice_bytes, size_t slice_pitch, int vec_bytes, void *stream);
