@@ -34,12 +34,28 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def trace_medians(stats_path: str) -> dict:
+    """Median dispatch duration (us) per kernel name from the kernel trace
+    written beside the stats file, when there is one."""
+    trace = stats_path.replace("kernel_stats.csv", "kernel_trace.csv")
+    if trace == stats_path or not os.path.exists(trace):
+        return {}
+    d: dict = {}
+    for r in csv.DictReader(open(trace)):
+        d.setdefault(r["Kernel_Name"], []).append(
+            (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    return {k: statistics.median(v) for k, v in d.items()}
+
+
 def stats_table(path: str) -> str:
     rows = list(csv.DictReader(open(path)))
-    out = ["| kernel | calls | avg us | min us | max us | total % |",
-           "|---|---:|---:|---:|---:|---:|"]
+    med = trace_medians(path)
+    out = ["| kernel | calls | avg us | median us | min us | max us | total % |",
+           "|---|---:|---:|---:|---:|---:|---:|"]
     for r in rows:
+        m = med.get(r["Name"])
         out.append(f"| `{r['Name']}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                   f"{'%.1f' % m if m is not None else '-'} | "
                    f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
                    f"{float(r['Percentage']):.1f} |")
     return "\n".join(out)
