@@ -366,27 +366,34 @@ def bench_c1_stripes(args, stream, out, log):
 
 def bench_layout(args, stream, out, log):
     """Symbol-major <-> bit-sliced conversion of one 64 MiB block (GF(2^8)
-    byte symbols and GF(2^10) 16-bit symbols)."""
+    byte symbols and GF(2^10) 16-bit symbols), with slices at a pitch of
+    S + 4 KiB (as the C1 stripe) and packed (pitch S, a power of two here)."""
     import torch
 
     import paper_1709_00178_amd as P
     res = {}
     for w, nsym in ((8, 64 << 20), (10, 32 << 20)):
         sb = nsym * (1 if w <= 8 else 2)
+        S = nsym // 8
         sym = torch.empty(sb, dtype=torch.uint8, device="cuda")
         P.fill_random(sym, 123)
-        sl = torch.empty(w * (nsym // 8), dtype=torch.uint8, device="cuda")
         back = torch.empty_like(sym)
-        to = lambda: P.to_sliced(w, sym, sl, n_symbols=nsym, stream=stream)
-        fr = lambda: P.from_sliced(w, sl, back, n_symbols=nsym, stream=stream)
-        to(); fr()
-        t_ms = min(batch_time_ms(to, 20, stream) for _ in range(2))
-        f_ms = min(batch_time_ms(fr, 20, stream) for _ in range(2))
-        moved = sb + sl.numel()
-        res[f"w{w}"] = {"symbols": nsym, "to_sliced_GBps": round(moved / (t_ms * 1e-3) / 1e9, 1),
-                        "from_sliced_GBps": round(moved / (f_ms * 1e-3) / 1e9, 1),
-                        "to_ms": round(t_ms, 4), "from_ms": round(f_ms, 4)}
-        del sym, sl, back
+        moved = sb + w * S
+        r = {"symbols": nsym}
+        for name, pitch in (("", S + 4096), ("packed_", S)):
+            sl = torch.empty((w - 1) * pitch + S, dtype=torch.uint8, device="cuda")
+            to = lambda: P.to_sliced(w, sym, sl, n_symbols=nsym, pitch=pitch, stream=stream)
+            fr = lambda: P.from_sliced(w, sl, back, n_symbols=nsym, pitch=pitch, stream=stream)
+            to(); fr()
+            t_ms = min(batch_time_ms(to, 20, stream) for _ in range(2))
+            f_ms = min(batch_time_ms(fr, 20, stream) for _ in range(2))
+            r[f"{name}to_sliced_GBps"] = round(moved / (t_ms * 1e-3) / 1e9, 1)
+            r[f"{name}from_sliced_GBps"] = round(moved / (f_ms * 1e-3) / 1e9, 1)
+            if not name:
+                r.update({"slice_pitch": pitch, "to_ms": round(t_ms, 4), "from_ms": round(f_ms, 4)})
+            del sl
+        res[f"w{w}"] = r
+        del sym, back
     out["layout_conversion"] = res
     torch.cuda.empty_cache()
 

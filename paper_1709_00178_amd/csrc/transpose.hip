@@ -37,6 +37,23 @@ __device__ __forceinline__ uint64_t transpose8(uint64_t x) {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
+// Byte select from the 8 bytes {hi, lo} (lo = bytes 0-3, hi = bytes 4-7):
+// result byte i = byte (sel >> 8i) & 0xFF of them, 12 gives zero.
+__device__ __forceinline__ uint32_t bsel(uint32_t hi, uint32_t lo, uint32_t sel) {
+  return __builtin_amdgcn_perm(hi, lo, sel);
+}
+__device__ __forceinline__ uint32_t lo32(uint64_t x) { return (uint32_t)x; }
+__device__ __forceinline__ uint32_t hi32(uint64_t x) { return (uint32_t)(x >> 32); }
+
+// Byte b (0..7) of each of x0..x3, in that order: one 32-bit word.
+__device__ __forceinline__ uint32_t gather_byte(uint64_t x0, uint64_t x1, uint64_t x2, uint64_t x3,
+                                                int b) {
+  const uint32_t sel = 0x0C0C0000u | ((4u + (b & 3)) << 8) | (uint32_t)(b & 3);
+  const uint32_t p01 = b < 4 ? bsel(lo32(x1), lo32(x0), sel) : bsel(hi32(x1), hi32(x0), sel);
+  const uint32_t p23 = b < 4 ? bsel(lo32(x3), lo32(x2), sel) : bsel(hi32(x3), hi32(x2), sel);
+  return bsel(p23, p01, 0x05040100u);
+}
+
 // BYTES = bytes per symbol (1 or 2).  Lane g: symbols 32g .. 32g+31.  The
 // lane count is a multiple of 16, so the last wave may be partial: 16-byte
 // units owned by lanes past the end are neither loaded nor stored.
@@ -74,16 +91,13 @@ __global__ __launch_bounds__(kTransposeWG) void to_sliced_kernel(const uint8_t *
       lo[q] = transpose8(v[q]);
       hi[q] = 0;
     } else {
-      // symbols 8q .. 8q+7 are words 2q and 2q+1: split low and high bytes
+      // symbols 8q .. 8q+7 are words 2q and 2q+1: the even bytes of both
+      // are the symbols' low bytes, the odd bytes their high bytes
       const uint64_t a = v[2 * q], b = v[2 * q + 1];
-      uint64_t l = 0, h = 0;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        l |= ((a >> (16 * i)) & 0xFFull) << (8 * i);
-        l |= ((b >> (16 * i)) & 0xFFull) << (8 * (i + 4));
-        h |= ((a >> (16 * i + 8)) & 0xFFull) << (8 * i);
-        h |= ((b >> (16 * i + 8)) & 0xFFull) << (8 * (i + 4));
-      }
+      const uint64_t l = ((uint64_t)bsel(hi32(b), lo32(b), 0x06040200u) << 32) |
+                         bsel(hi32(a), lo32(a), 0x06040200u);
+      const uint64_t h = ((uint64_t)bsel(hi32(b), lo32(b), 0x07050301u) << 32) |
+                         bsel(hi32(a), lo32(a), 0x07050301u);
       lo[q] = transpose8(l);
       hi[q] = transpose8(h);
     }
@@ -93,12 +107,8 @@ __global__ __launch_bounds__(kTransposeWG) void to_sliced_kernel(const uint8_t *
 #pragma unroll
   for (int t = 0; t < 8 * BYTES; ++t) {
     if ((uint32_t)t >= w) break;
-    uint32_t word = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const uint64_t src8 = t < 8 ? lo[q] : hi[q];
-      word |= (uint32_t)((src8 >> (8 * (t & 7))) & 0xFFull) << (8 * q);
-    }
+    const uint32_t word = t < 8 ? gather_byte(lo[0], lo[1], lo[2], lo[3], t)
+                                : gather_byte(hi[0], hi[1], hi[2], hi[3], t - 8);
     *(uint32_t *)(dst + (size_t)t * pitch) = word;
   }
 }
@@ -121,15 +131,17 @@ __global__ __launch_bounds__(kTransposeWG) void from_sliced_kernel(const uint8_t
     words[t] = (live && (uint32_t)t < w)
                    ? __builtin_nontemporal_load((const uint32_t *)(src + (size_t)t * pitch))
                    : 0u;
+  // byte t of lo[q] (hi[q]) = byte q of slice word t (t + 8)
 #pragma unroll
-  for (int t = 0; t < 8 * BYTES; ++t) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const uint64_t b = (words[t] >> (8 * q)) & 0xFFu;
-      if (t < 8)
-        lo[q] |= b << (8 * t);
-      else
-        hi[q] |= b << (8 * (t - 8));
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t sel = 0x0C0C0000u | ((4u + q) << 8) | (uint32_t)q;
+    const uint32_t l0 = bsel(bsel(words[3], words[2], sel), bsel(words[1], words[0], sel), 0x05040100u);
+    const uint32_t l1 = bsel(bsel(words[7], words[6], sel), bsel(words[5], words[4], sel), 0x05040100u);
+    lo[q] = ((uint64_t)l1 << 32) | l0;
+    if constexpr (BYTES == 2) {
+      const uint32_t h0 = bsel(bsel(words[11], words[10], sel), bsel(words[9], words[8], sel), 0x05040100u);
+      const uint32_t h1 = bsel(bsel(words[15], words[14], sel), bsel(words[13], words[12], sel), 0x05040100u);
+      hi[q] = ((uint64_t)h1 << 32) | h0;
     }
   }
   uint64_t v[4 * BYTES];
@@ -140,16 +152,11 @@ __global__ __launch_bounds__(kTransposeWG) void from_sliced_kernel(const uint8_t
       v[q] = l;
     } else {
       const uint64_t h = transpose8(hi[q]);
-      uint64_t a = 0, b = 0;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        a |= ((l >> (8 * i)) & 0xFFull) << (16 * i);
-        a |= ((h >> (8 * i)) & 0xFFull) << (16 * i + 8);
-        b |= ((l >> (8 * (i + 4))) & 0xFFull) << (16 * i);
-        b |= ((h >> (8 * (i + 4))) & 0xFFull) << (16 * i + 8);
-      }
-      v[2 * q] = a;
-      v[2 * q + 1] = b;
+      // interleave: symbol i = low byte i of l, high byte i of h
+      v[2 * q] = ((uint64_t)bsel(lo32(h), lo32(l), 0x07030602u) << 32) |
+                 bsel(lo32(h), lo32(l), 0x05010400u);
+      v[2 * q + 1] = ((uint64_t)bsel(hi32(h), hi32(l), 0x07030602u) << 32) |
+                     bsel(hi32(h), hi32(l), 0x05010400u);
     }
   }
 #pragma unroll
