@@ -315,6 +315,19 @@ int pyrit_batch_info(const pyrit_batch *batch, int *n_passes, int *n_work_items,
 /* Release the batch.  The caller must ensure no stream still runs it. */
 void pyrit_batch_destroy(pyrit_batch *batch);
 
+/* The work pyrit_batch_create would set up for the same items and tune,
+ * computed on the host only: nothing is allocated on or sent to the device
+ * and the block pointers are not dereferenced (they must still be 16-byte
+ * aligned), so it serves capacity planning.  The persistent modes need
+ * tune->grid > 0, since their resident grid is otherwise a device query.
+ * Outputs as pyrit_batch_info (any pointer may be NULL); xcd_bytes (8
+ * entries) receives the bytes moved by each XCD's contiguous item range in
+ * grid mode with xcd_order = 1 (the ranges are cut to equal bytes), zeros
+ * otherwise.  Errors as pyrit_batch_create, without the device ones. */
+int pyrit_batch_describe(const pyrit_batch_item *items, int n_items, const pyrit_tune *tune,
+                         int *n_passes, int *n_work_items, uint64_t *moved_bytes, int *grid,
+                         uint64_t *xcd_bytes);
+
 /* ------------------------------------------------------------------ serving
  * A request loop with continuous batching.  Requests arrive over time; each
  * is admitted (FIFO) once its output blocks fit in the server's device pool,

@@ -193,6 +193,54 @@ class Plan:
                                      _stream_handle(stream)))
 
 
+def _batch_items(items):
+    """C item array for batch items; returns it with what keeps it alive."""
+    from ._lib import BatchItem
+    keep = []
+    arr = (BatchItem * max(1, len(items)))()
+    for i, it in enumerate(items):
+        plan, erased, blocks, S = it[:4]
+        pitch = it[4] if len(it) > 4 else 0
+        if len(blocks) != plan.k + plan.m:
+            raise ValueError("each item needs k + m block entries")
+        er = (ctypes.c_int * max(1, len(erased)))(*erased)
+        bl = _ptr_array(blocks)
+        keep += [er, bl, plan]
+        arr[i].plan = plan._h
+        arr[i].n_erased = len(erased)
+        arr[i].erased = ctypes.cast(er, ctypes.POINTER(ctypes.c_int))
+        arr[i].blocks = ctypes.cast(bl, ctypes.POINTER(ctypes.c_void_p))
+        arr[i].slice_bytes = S
+        arr[i].slice_pitch = pitch
+    return arr, keep
+
+
+def _batch_tune(mode, tile_bytes, grid, wg_threads, xcd_order, split_k):
+    from ._lib import BATCH_MODES, Tune
+    if mode not in BATCH_MODES:
+        raise ValueError(f"mode must be one of {sorted(BATCH_MODES)}")
+    return Tune(BATCH_MODES[mode], tile_bytes, grid, wg_threads, xcd_order, split_k)
+
+
+def batch_describe(items, mode: str = "grid", tile_bytes: int = 0, grid: int = 0,
+                   wg_threads: int = 0, xcd_order: int = 0, split_k: int = 0) -> dict:
+    """The work a `Batch` of these items would launch, computed on the host
+    (pyrit_batch_describe): passes, work items, bytes moved, workgroups, and
+    the bytes of each XCD's item range (grid mode with xcd_order=1).  Block
+    entries may be plain integer addresses; nothing touches the device."""
+    items = list(items)
+    arr, keep = _batch_items(items)
+    tune = _batch_tune(mode, tile_bytes, grid, wg_threads, xcd_order, split_k)
+    np_, ni, gr = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    mv = ctypes.c_uint64()
+    xb = (ctypes.c_uint64 * 8)()
+    _check(lib().pyrit_batch_describe(arr, len(items), ctypes.byref(tune), ctypes.byref(np_),
+                                      ctypes.byref(ni), ctypes.byref(mv), ctypes.byref(gr), xb))
+    del keep
+    return {"passes": np_.value, "work_items": ni.value, "moved_bytes": mv.value,
+            "grid": gr.value, "xcd_bytes": list(xb)}
+
+
 class Batch:
     """Many stripes coded by one batch-kernel launch.
 
@@ -210,28 +258,10 @@ class Batch:
         if launch not in ("graph", "direct"):
             raise ValueError("launch must be 'graph' or 'direct'")
         self.launch_form = launch
-        from ._lib import BATCH_MODES, BatchItem, Tune
         items = list(items)
-        self._keep = []
-        arr = (BatchItem * max(1, len(items)))()
-        for i, it in enumerate(items):
-            plan, erased, blocks, S = it[:4]
-            pitch = it[4] if len(it) > 4 else 0
-            if len(blocks) != plan.k + plan.m:
-                raise ValueError("each item needs k + m block entries")
-            er = (ctypes.c_int * max(1, len(erased)))(*erased)
-            bl = _ptr_array(blocks)
-            self._keep += [er, bl, plan]
-            arr[i].plan = plan._h
-            arr[i].n_erased = len(erased)
-            arr[i].erased = ctypes.cast(er, ctypes.POINTER(ctypes.c_int))
-            arr[i].blocks = ctypes.cast(bl, ctypes.POINTER(ctypes.c_void_p))
-            arr[i].slice_bytes = S
-            arr[i].slice_pitch = pitch
-        if mode not in BATCH_MODES:
-            raise ValueError(f"mode must be one of {sorted(BATCH_MODES)}")
+        arr, self._keep = _batch_items(items)
         self.mode = mode
-        tune = Tune(BATCH_MODES[mode], tile_bytes, grid, wg_threads, xcd_order, split_k)
+        tune = _batch_tune(mode, tile_bytes, grid, wg_threads, xcd_order, split_k)
         h = ctypes.c_void_p()
         _check(lib().pyrit_batch_create(arr, len(items), ctypes.byref(tune), ctypes.byref(h)))
         self._h = h

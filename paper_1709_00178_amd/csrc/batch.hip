@@ -507,6 +507,7 @@ int build_batch_image(const pyrit_batch_item *items, int n_items, const pyrit_tu
   // grid mode with XCD order: eight contiguous ranges of equal bytes moved
   bi->xcd_start.assign(kXcds + 1, (uint32_t)work.size());
   bi->xcd_start[0] = 0;
+  bi->xcd_bytes.assign(kXcds, 0);
   uint32_t longest = 0;
   if (!persistent && t.xcd_order) {
     auto cost = [&](const WorkItem &it) {
@@ -522,8 +523,11 @@ int build_batch_image(const pyrit_batch_item *items, int n_items, const pyrit_tu
       while (x < kXcds && acc * kXcds >= total * x) bi->xcd_start[x++] = (uint32_t)i;
       acc += cost(work[i]);
     }
-    for (uint32_t y = 0; y < kXcds; ++y)
+    for (uint32_t y = 0; y < kXcds; ++y) {
       longest = std::max(longest, bi->xcd_start[y + 1] - bi->xcd_start[y]);
+      for (uint32_t i = bi->xcd_start[y]; i < bi->xcd_start[y + 1]; ++i)
+        bi->xcd_bytes[y] += cost(work[i]);
+    }
   }
 
   // Image: counters | starts | passes | items | pointer and lift tables.
@@ -683,5 +687,29 @@ int pyrit_batch_info(const pyrit_batch *batch, int *n_passes, int *n_work_items,
 }
 
 void pyrit_batch_destroy(pyrit_batch *batch) { delete batch; }
+
+int pyrit_batch_describe(const pyrit_batch_item *items, int n_items, const pyrit_tune *tune,
+                         int *n_passes, int *n_work_items, uint64_t *moved_bytes, int *grid,
+                         uint64_t *xcd_bytes) {
+  if (n_items < 0 || (n_items > 0 && !items)) return PYRIT_EINVAL;
+  pyrit_tune t{};
+  if (tune) t = *tune;
+  int rc = batch_check_tune(&t);
+  if (rc) return rc;
+  // the resident grid of the persistent modes is a device query: take it
+  // from the caller instead
+  if (t.mode != kModeGrid && t.grid <= 0) return PYRIT_EINVAL;
+  const int resident = t.mode == kModeQueue ? std::max(t.grid, kGroups) : t.grid;
+  BatchImage bi;
+  rc = build_batch_image(items, n_items, t, t.mode == kModeGrid ? 0 : resident, 0, &bi);
+  if (rc) return rc;
+  if (n_passes) *n_passes = (int)bi.n_passes;
+  if (n_work_items) *n_work_items = (int)bi.n_items;
+  if (moved_bytes) *moved_bytes = bi.moved;
+  if (grid) *grid = bi.grid;
+  if (xcd_bytes)
+    for (uint32_t x = 0; x < kXcds; ++x) xcd_bytes[x] = bi.xcd_bytes[x];
+  return PYRIT_OK;
+}
 
 }  // extern "C"

@@ -106,6 +106,7 @@ struct BatchImage {
   int grid = 0, wg = 128, mode = 0, xcd_order = 0, split = 1;
   uint64_t moved = 0;
   std::vector<uint32_t> xcd_start;  // grid mode with XCD order: per-XCD item ranges
+  std::vector<uint64_t> xcd_bytes;  // bytes moved by each of those ranges
 };
 int batch_check_tune(pyrit_tune *t);
 int batch_resident_grid(const pyrit_tune &t, int *grid);

@@ -137,6 +137,10 @@ def test_c3_all_4096_uneven_stripes_one_launch(mode, xcd, split):
     b = P.Batch(items, mode=mode, xcd_order=xcd, split_k=split)
     info = b.info()
     assert info["moved_bytes"] == sum(s.moved_bytes() for s in stripes)
+    if mode == "grid":  # the host-only description sets up the same launch
+        d = P.batch_describe(items, mode=mode, xcd_order=xcd, split_k=split)
+        assert [d[f] for f in ("passes", "work_items", "moved_bytes", "grid")] == \
+               [info[f] for f in ("passes", "work_items", "moved_bytes", "grid")]
     _clear_outputs(bufs, 0x77)
     b.launch()
     sync()
