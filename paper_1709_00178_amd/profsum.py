@@ -1,6 +1,7 @@
 """Summaries of rocprofv3 CSV output for the committed profiles.
 
-    python -m paper_1709_00178_amd.profsum stats  <run_kernel_stats.csv>  --cmd "..." > out.md
+    python -m paper_1709_00178_amd.profsum stats  <run_kernel_stats.csv>  --cmd "..." \\
+        [--marker NAME --kernel NAME] > out.md
     python -m paper_1709_00178_amd.profsum traffic --fetch <dir> --write <dir> --kernel NAME \\
         --copy-bytes N --record KEY [--algorithmic BYTES] --cmd "..." > out.md
 
@@ -61,6 +62,24 @@ def stats_table(path: str) -> str:
     return "\n".join(out)
 
 
+def marked_launches(stats_path: str, marker: str, kernel: str):
+    """Durations (us) of the dispatches of `kernel` that ran wholly inside
+    the marker range `marker` (rocprofv3 --marker-trace beside the stats)."""
+    mpath = stats_path.replace("kernel_stats.csv", "marker_api_trace.csv")
+    tpath = stats_path.replace("kernel_stats.csv", "kernel_trace.csv")
+    ranges = [(int(r["Start_Timestamp"]), int(r["End_Timestamp"]))
+              for r in csv.DictReader(open(mpath)) if r["Function"] == marker]
+    if len(ranges) != 1:
+        raise SystemExit(f"marker '{marker}' found {len(ranges)} times")
+    t0, t1 = ranges[0]
+    out = []
+    for r in csv.DictReader(open(tpath)):
+        a, b = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+        if kernel in r["Kernel_Name"] and t0 <= a and b <= t1:
+            out.append((b - a) / 1e3)
+    return out
+
+
 def counter_means(directory: str, counter: str) -> dict:
     """Mean value of `counter` per kernel name over its dispatches."""
     files = glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)
@@ -85,6 +104,8 @@ def main():
     a = sub.add_parser("stats")
     a.add_argument("csv")
     a.add_argument("--cmd", required=True)
+    a.add_argument("--marker", default="")
+    a.add_argument("--kernel", default="")
     b = sub.add_parser("traffic")
     b.add_argument("--fetch", required=True)
     b.add_argument("--write", required=True)
@@ -98,6 +119,12 @@ def main():
     if args.what == "stats":
         print(f"Command: `{args.cmd}`\n")
         print(stats_table(args.csv))
+        if args.marker:
+            d = marked_launches(args.csv, args.marker, args.kernel)
+            print(f"\nInside the marker range `{args.marker}` (the bench's timed steps): "
+                  f"{len(d)} launches of `{args.kernel}`, mean {statistics.fmean(d):.1f} us, "
+                  f"median {statistics.median(d):.1f} us, min {min(d):.1f} us, "
+                  f"max {max(d):.1f} us.")
         return
     fetch = counter_means(args.fetch, "FETCH_SIZE")
     write = counter_means(args.write, "WRITE_SIZE")
