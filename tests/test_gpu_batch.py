@@ -147,6 +147,55 @@ def test_c3_all_4096_uneven_stripes_one_launch(mode, xcd, split):
     _check_stripes(stripes, bufs, plans, ncols=10)
 
 
+def test_c1_full_size_as_benched():
+    """The headline stripe in the benchmark's own layout and launch: 64 MiB
+    blocks, slices 8 MiB + 4 KiB apart, blocks 4352 B apart, the grid
+    executor with 128-thread split-K workgroups, direct dispatch.  Sampled
+    columns of every parity slice against the oracle; the gaps between
+    slices untouched; then the workload's 4-erasure decode the same way."""
+    import dataclasses
+    torch = torch_mod()
+    st = dataclasses.replace(W.c1(), pad=4096)
+    plan = P.Plan(st.w, st.n, st.p, st.k, st.m)
+    skew = 4352
+    stride = (st.block_len + 255) // 256 * 256 + skew
+    pool = torch.empty(stride * (st.k + st.m + 4) + 4096, dtype=torch.uint8, device="cuda")
+    blocks = [pool[i * stride:i * stride + st.block_len] for i in range(st.k + st.m)]
+    for j in range(st.k):
+        P.fill_random(blocks[j], st.key(j), nrandom=st.nrandom)
+    for b in blocks[st.k:]:
+        b.fill_(0xA5)
+    b = P.Batch([(plan, [], blocks, st.S, st.pitch)], mode="grid", wg_threads=128, xcd_order=0,
+                split_k=2, launch="direct")
+    b.run()
+    sync()
+    cols = sample_cols(st.S, 2048, 3)
+    want = oracle_cols(st, plan.G, range(st.k), cols)
+    idx = torch.as_tensor((np.arange(st.w)[:, None] * st.pitch + cols[None, :]).reshape(-1),
+                          device="cuda")
+    for i in range(st.m):
+        assert np.array_equal(blocks[st.k + i][idx].cpu().numpy(), want[i]), i
+        for t in range(st.w):
+            gap = blocks[st.k + i][t * st.pitch + st.S:(t + 1) * st.pitch]
+            assert bool((gap == 0xA5).all()), (i, t)
+    # decode: the erased blocks come back bit-exact
+    er = list(W.c1_erasure_patterns()[0])
+    spare = [pool[(st.k + st.m + q) * stride:(st.k + st.m + q) * stride + st.block_len]
+             for q in range(len(er))]
+    dec = [spare[er.index(i)] if i in er else blk for i, blk in enumerate(blocks)]
+    d = P.Batch([(plan, er, dec, st.S, st.pitch)], mode="grid", wg_threads=128, split_k=2,
+                launch="direct")
+    d.run()
+    sync()
+    for q, e in enumerate(er):
+        for t in range(st.w):
+            sl = slice(t * st.pitch, t * st.pitch + st.S)
+            assert torch.equal(spare[q][sl], blocks[e][sl]), (e, t)
+    b.close()
+    d.close()
+    del pool
+
+
 def test_c1_code_64_stripes_one_launch():
     """The headline code over 64 stripes of 1 MiB blocks in one launch (the
     bench's many-stripe leg), every stripe against the oracle."""
