@@ -46,7 +46,7 @@ def _check_stripes(stripes, bufs, plans, ncols=16, seed=0):
         G = plan.decode_matrix(list(st.erased))[1] if st.erased else plan.G
         cols = sample_cols(st.S, ncols, seed + st.stripe)
         want = oracle_cols(st, G, ins, cols, nthreads=1)
-        idx = torch.as_tensor((np.arange(st.w)[:, None] * st.S + cols[None, :]).reshape(-1),
+        idx = torch.as_tensor((np.arange(st.w)[:, None] * st.pitch + cols[None, :]).reshape(-1),
                               device="cuda")
         got_all = torch.stack([blocks[b][idx] for b in outs]).cpu().numpy()
         for r, b in enumerate(outs):
@@ -55,7 +55,8 @@ def _check_stripes(stripes, bufs, plans, ncols=16, seed=0):
 
 def _build(stripes, plans, arena):
     bufs = [stripe_buffers(st, arena) for st in stripes]
-    items = [(plans.get(st), list(st.erased), bufs[i][0], st.S) for i, st in enumerate(stripes)]
+    items = [(plans.get(st), list(st.erased), bufs[i][0], st.S, st.pitch)
+             for i, st in enumerate(stripes)]
     return bufs, items
 
 
@@ -194,6 +195,26 @@ def test_c1_full_size_as_benched():
     b.close()
     d.close()
     del pool
+
+
+@pytest.mark.parametrize("xcd", [0, 1])
+def test_c3_with_256_byte_aligned_slices(xcd):
+    """The uneven batch as the benchmark codes it: every slice pitch rounded
+    up to 256 bytes (blocks random over their whole memory, so B = w * S),
+    the split-K grid executor in both item orders."""
+    import dataclasses
+    stripes = [dataclasses.replace(st, B=st.w * st.S, pad=-(-st.S // 256) * 256 - st.S)
+               for st in W.c3()]
+    assert sum(st.pad > 0 for st in stripes) > len(stripes) // 2
+    plans = PlanCache()
+    arena = Arena(sum(stripe_bytes_needed(s) for s in stripes) + 4096)
+    bufs, items = _build(stripes, plans, arena)
+    b = P.Batch(items, mode="grid", wg_threads=128, split_k=2, xcd_order=xcd, launch="direct")
+    _clear_outputs(bufs, 0x3C)
+    b.run()
+    sync()
+    _check_stripes(stripes, bufs, plans, ncols=10, seed=5)
+    b.close()
 
 
 def test_c1_code_64_stripes_one_launch():
