@@ -22,8 +22,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, 8 TB/s
-KERNEL_SOURCES = ["paper_1709_00178_amd/csrc/ring_kernels.hpp",
+KERNEL_SOURCES = ["paper_1709_00178_amd/csrc/rings.hpp",
+                  "paper_1709_00178_amd/csrc/ring_kernels.hpp",
                   "paper_1709_00178_amd/csrc/plain_impl.hpp",
+                  "paper_1709_00178_amd/csrc/batch_abi.hpp",
                   "paper_1709_00178_amd/csrc/batch.hip"]
 
 

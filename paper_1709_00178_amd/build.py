@@ -21,6 +21,7 @@ SOURCES = [
     "serve.cpp",
     "device_api.hip",
     "batch.hip",
+    "batch_host.cpp",
     "transpose.hip",
     "plain_ring0.hip",
     "plain_ring1.hip",

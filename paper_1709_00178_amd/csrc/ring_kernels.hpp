@@ -19,7 +19,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "internal.hpp"
+#include "rings.hpp"
 
 namespace pyrit {
 namespace dev {

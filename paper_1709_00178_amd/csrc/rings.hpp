@@ -1,0 +1,54 @@
+// The rings with device kernels and the argument block of one coding pass:
+// everything the kernels are compiled from besides their own sources.
+#pragma once
+#include <stdint.h>
+
+#include "../../include/pyrit.h"
+
+namespace pyrit {
+
+// Outputs computed by one kernel pass: the accumulators of every output live
+// in registers, so a pass covers at most this many output blocks (the bound
+// of every per-pass array; each ring has its own limit, ring_max_out).
+constexpr int kMaxOut = 8;
+
+// Rings with a device kernel.  The kernels are templates on (w, n, p), so the
+// reduction modulo p and every rotation index are compile-time constants.
+// `parity` selects the parity transform (Sec. II-C.1, II-D.1) in place of the
+// embedding transform (Sec. II-C.2, II-D.2): data enter the ring with n - w
+// parity slices instead of zero slices, and results leave it by dropping
+// those slices instead of reducing modulo p.
+struct RingDesc {
+  int w, n;
+  uint32_t p;
+  bool parity;
+};
+constexpr int kNumRings = 8;
+constexpr RingDesc kRings[kNumRings] = {
+    {4, 5, 0x1Fu, false},     // all-one polynomial of degree 4 (Sec. II-C)
+    {8, 17, 0x139u, false},   // x^8+x^5+x^4+x^3+1, divides x^17+1
+    {8, 17, 0x1D7u, false},   // x^8+x^7+x^6+x^4+x^2+x+1, the other factor
+    {10, 11, 0x7FFu, false},  // all-one polynomial of degree 10
+    {6, 9, 0x49u, false},     // equally spaced x^6+x^3+1 (Sec. II-D)
+    {4, 5, 0x1Fu, true},      // the AOP and ESP rings again, parity transform
+    {10, 11, 0x7FFu, true},
+    {6, 9, 0x49u, true},
+};
+// Outputs per pass of a ring: outputs x n ring slices of accumulators stay
+// near 70 registers per lane (4 for n = 17, 6 for n = 11, 8 for n <= 9).
+constexpr int ring_max_out(int ring) {
+  return kRings[ring].n <= 9 ? 8 : kRings[ring].n <= 11 ? 6 : 4;
+}
+
+// Arguments of one coding pass: outputs out[r] (r < nout) are
+// sum_j lift[j][r] (*) in[j] in the ring, reduced mod p.
+struct PassArgs {
+  const uint8_t *in[PYRIT_KMAX];
+  uint8_t *out[kMaxOut];
+  uint32_t lift[PYRIT_KMAX][kMaxOut];
+  uint32_t k;
+  uint32_t S;      // column bytes per slice
+  uint32_t pitch;  // bytes from one slice to the next (>= S)
+};
+
+}  // namespace pyrit

@@ -18,6 +18,7 @@
 #include <thread>
 #include <vector>
 
+#include "batch_host.hpp"
 #include "internal.hpp"
 
 namespace pyrit {

@@ -22,8 +22,10 @@ import os
 import statistics
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL_SOURCES = ["paper_1709_00178_amd/csrc/ring_kernels.hpp",
+KERNEL_SOURCES = ["paper_1709_00178_amd/csrc/rings.hpp",
+                  "paper_1709_00178_amd/csrc/ring_kernels.hpp",
                   "paper_1709_00178_amd/csrc/plain_impl.hpp",
+                  "paper_1709_00178_amd/csrc/batch_abi.hpp",
                   "paper_1709_00178_amd/csrc/batch.hip"]
 
 
