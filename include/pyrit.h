@@ -278,9 +278,10 @@ typedef struct {
   int wg_threads;   /* 64, 128 or 256 threads per workgroup; 0 = 128 */
   int xcd_order;    /* grid mode, 0 or 1.  Workgroups are dealt round-robin
                        over the 8 XCDs; with 1 the workgroup-to-item map is
-                       permuted so that each XCD codes a contiguous eighth of
-                       the queue (0: workgroup i codes item i).  Persistent
-                       modes ignore it. */
+                       permuted so that each XCD codes a contiguous range of
+                       the queue, the ranges cut to equal bytes moved (0:
+                       workgroup i codes item i).  Persistent modes ignore
+                       it. */
   int split_k;      /* grid mode: waves sharing one column chunk, each coding
                        every split_k-th input block, partial sums combined in
                        LDS before the stores: 1, or 2 (128-thread workgroups
@@ -294,7 +295,9 @@ typedef struct pyrit_batch pyrit_batch;
  * pointer tables to device memory (one allocation owned by the batch) and
  * instantiate the hipGraph.  Nothing runs on the GPU yet.  tune may be NULL.
  * Items are validated like pyrit_encode / pyrit_decode; the first failing
- * item's code is returned and no batch is created. */
+ * item's code is returned and no batch is created.  The items of one batch
+ * run concurrently: no item may write a block (or slice bytes) that another
+ * item of the same batch reads or writes. */
 int pyrit_batch_create(const pyrit_batch_item *items, int n_items, const pyrit_tune *tune,
                        pyrit_batch **out);
 
