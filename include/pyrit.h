@@ -284,9 +284,10 @@ typedef struct {
                        it. */
   int split_k;      /* grid mode: waves sharing one column chunk, each coding
                        every split_k-th input block, partial sums combined in
-                       LDS before the stores: 1, or 2 (128-thread workgroups
-                       only); 0 = 2 for 128-thread grid workgroups, else 1.
-                       Persistent modes take 0 or 1. */
+                       LDS before the stores: 1, or 2 (128-thread workgroups:
+                       one pair of waves on one chunk; 256-thread: two pairs
+                       on adjacent chunks); 0 = 2 for 128-thread grid
+                       workgroups, else 1.  Persistent modes take 0 or 1. */
 } pyrit_tune;
 
 typedef struct pyrit_batch pyrit_batch;

@@ -23,6 +23,8 @@ from . import Batch
 CANDIDATES = [
     {"mode": "grid", "wg_threads": 128, "split_k": 2},
     {"mode": "grid", "wg_threads": 128, "split_k": 2, "xcd_order": 1},
+    {"mode": "grid", "wg_threads": 256, "split_k": 2},
+    {"mode": "grid", "wg_threads": 256, "split_k": 2, "xcd_order": 1},
     {"mode": "grid", "wg_threads": 64, "split_k": 1},
     {"mode": "grid", "wg_threads": 128, "split_k": 1},
     {"mode": "grid", "wg_threads": 256, "split_k": 1},
@@ -82,7 +84,7 @@ def signature(items) -> str:
     if n == 0:
         return "empty"
     return "|".join([
-        "v4", ",".join(f"{w}/{nn}/{p:x}" for w, nn, p in sorted(rings)),
+        "v5", ",".join(f"{w}/{nn}/{p:x}" for w, nn, p in sorted(rings)),
         f"k{min(ks)}-{max(ks)}", f"o{min(outs)}-{max(outs)}",
         f"s{int(math.log2(min(sizes)))}-{int(math.log2(max(sizes)))}",
         f"d{round(10 * dec / n)}", f"n{int(math.log2(n))}", f"a{align}",

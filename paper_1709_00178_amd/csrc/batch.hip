@@ -131,12 +131,14 @@ __device__ __forceinline__ void code_item(const AS4 PassDesc *passes, const AS4 
 // differ up to 10x in cost), and the grid holds eight times the longest
 // range: workgroups past the end of their XCD's range leave at once.
 //
-// KS = 2 (split-K, 128-thread workgroups only): the two waves share one
-// chunk, each coding every other input block (see code_column).
+// KS = 2 (split-K): each pair of waves shares one chunk, each wave coding
+// every other input block (see code_column); a 256-thread workgroup holds
+// two pairs on adjacent chunks.
 template <int WG, bool XCD_ORDER, int KS>
 __global__ __launch_bounds__(WG) void batch_grid_kernel(const BatchArgs a) {
-  static_assert(KS == 1 || WG == 64 * KS, "split-K workgroups hold one chunk");
-  __shared__ __attribute__((aligned(16))) uint32_t xch[KS > 1 ? xch_dwords() : 1];
+  static_assert(KS == 1 || WG % (64 * KS) == 0, "split-K workgroups hold whole pairs");
+  constexpr int kPairs = WG / 64 / KS;  // chunks per workgroup
+  __shared__ __attribute__((aligned(16))) uint32_t xch[KS > 1 ? kPairs * xch_dwords() : 1];
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const AS4 uint32_t *starts = (const AS4 uint32_t *)a.starts;
@@ -161,19 +163,25 @@ __global__ __launch_bounds__(WG) void batch_grid_kernel(const BatchArgs a) {
   const uint32_t chunk = chunk_bytes(ring);
   const uint32_t base = ((b - first) * (WG / 64 / KS) + wave / KS) * chunk;
   const uint32_t part = wave % KS;
-  // a workgroup of one chunk never starts past the end of its pass; with
-  // several, both waves of a split-K pair leave together
-  if constexpr (WG / 64 / KS > 1)
-    if (base >= pd.S) return;
+  // A workgroup's first chunk never starts past the end of its pass; a later
+  // one may.  Such a chunk has nothing to code.  A split-K pair still meets
+  // the one barrier the other pairs of its workgroup wait at.
+  if constexpr (kPairs > 1) {
+    if (base >= pd.S) {
+      if constexpr (KS > 1) __syncthreads();
+      return;
+    }
+  }
+  uint32_t *px = xch + (KS > 1 ? (wave / KS) * xch_dwords() : 0);
   switch (ring) {
-    case 0: run_chunk<0, KS>(pd, base, lane, part, xch); break;
-    case 1: run_chunk<1, KS>(pd, base, lane, part, xch); break;
-    case 2: run_chunk<2, KS>(pd, base, lane, part, xch); break;
-    case 3: run_chunk<3, KS>(pd, base, lane, part, xch); break;
-    case 4: run_chunk<4, KS>(pd, base, lane, part, xch); break;
-    case 5: run_chunk<5, KS>(pd, base, lane, part, xch); break;
-    case 6: run_chunk<6, KS>(pd, base, lane, part, xch); break;
-    case 7: run_chunk<7, KS>(pd, base, lane, part, xch); break;
+    case 0: run_chunk<0, KS>(pd, base, lane, part, px); break;
+    case 1: run_chunk<1, KS>(pd, base, lane, part, px); break;
+    case 2: run_chunk<2, KS>(pd, base, lane, part, px); break;
+    case 3: run_chunk<3, KS>(pd, base, lane, part, px); break;
+    case 4: run_chunk<4, KS>(pd, base, lane, part, px); break;
+    case 5: run_chunk<5, KS>(pd, base, lane, part, px); break;
+    case 6: run_chunk<6, KS>(pd, base, lane, part, px); break;
+    case 7: run_chunk<7, KS>(pd, base, lane, part, px); break;
     default: break;
   }
 }
@@ -223,10 +231,11 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(5))) void ba
 }
 
 static const void *grid_fn(int wg, bool xcd, int split) {
-  if (split == 2)
-    return wg == 128 ? (xcd ? (const void *)batch_grid_kernel<128, true, 2>
-                            : (const void *)batch_grid_kernel<128, false, 2>)
-                     : nullptr;
+  if (split == 2) switch (wg) {
+      case 128: return xcd ? (const void *)batch_grid_kernel<128, true, 2> : (const void *)batch_grid_kernel<128, false, 2>;
+      case 256: return xcd ? (const void *)batch_grid_kernel<256, true, 2> : (const void *)batch_grid_kernel<256, false, 2>;
+      default: return nullptr;
+    }
   switch (wg) {
     case 64: return xcd ? (const void *)batch_grid_kernel<64, true, 1> : (const void *)batch_grid_kernel<64, false, 1>;
     case 128: return xcd ? (const void *)batch_grid_kernel<128, true, 1> : (const void *)batch_grid_kernel<128, false, 1>;

@@ -95,7 +95,7 @@ int batch_check_tune(pyrit_tune *t) {
   if (t->wg_threads != 64 && t->wg_threads != 128 && t->wg_threads != 256) return PYRIT_EINVAL;
   if (t->split_k < 0 || t->split_k > 2) return PYRIT_EINVAL;
   if (t->split_k == 0) t->split_k = (t->mode == kModeGrid && t->wg_threads == 128) ? 2 : 1;
-  if (t->split_k == 2 && (t->mode != kModeGrid || t->wg_threads != 128)) return PYRIT_EINVAL;
+  if (t->split_k == 2 && (t->mode != kModeGrid || t->wg_threads == 64)) return PYRIT_EINVAL;
   return PYRIT_OK;
 }
 

@@ -95,6 +95,19 @@ def test_wide_codes_split_into_passes():
     assert d["moved_bytes"] == (3 * 10 + 9) * st.w * st.S
 
 
+def test_two_split_k_pairs_per_workgroup(c3):
+    """256-thread split-K workgroups hold two pairs on adjacent chunks: half
+    as many items as 128-thread ones, and the same bytes."""
+    stripes, items = c3
+    one = P.batch_describe(items, wg_threads=128, split_k=2)
+    two = P.batch_describe(items, wg_threads=256, split_k=2)
+    assert two["moved_bytes"] == one["moved_bytes"]
+    assert two["work_items"] == sum(math.ceil(st.S / (2 * 256 * (2 if st.w == 4 else 1)))
+                                    for st in stripes)
+    assert one["work_items"] == sum(math.ceil(st.S / (256 * (2 if st.w == 4 else 1)))
+                                    for st in stripes)
+
+
 def test_persistent_modes_need_a_grid(c3):
     stripes, items = c3
     for mode in ("queue", "static"):
@@ -116,7 +129,7 @@ def test_describe_errors():
         P.batch_describe([(plan, er, blocks, S, S - 64)])
     assert e.value.code == EINVAL
     with pytest.raises(P.PyritError) as e:
-        P.batch_describe([(plan, er, blocks, S, pitch)], split_k=2, wg_threads=256)
+        P.batch_describe([(plan, er, blocks, S, pitch)], split_k=2, wg_threads=64)
     assert e.value.code == EINVAL
     with pytest.raises(P.PyritError) as e:
         P.batch_describe([(plan, [0, 1, 2], blocks, S, pitch)])

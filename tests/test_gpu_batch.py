@@ -80,7 +80,7 @@ def test_batch_single_stripe_every_shape():
               ("static", 512, 0, 1), ("static", 4096, 0, 1)]
     for wg in [64, 128, 256]:
         for mode, tile, xcd, split in shapes:
-            if split == 2 and wg != 128:
+            if split == 2 and wg == 64:
                 continue
             b = P.Batch(items, mode=mode, tile_bytes=tile, wg_threads=wg, xcd_order=xcd,
                         split_k=split)
@@ -197,8 +197,8 @@ def test_c1_full_size_as_benched():
     del pool
 
 
-@pytest.mark.parametrize("xcd", [0, 1])
-def test_c3_with_256_byte_aligned_slices(xcd):
+@pytest.mark.parametrize("xcd,wg", [(0, 128), (1, 128), (0, 256), (1, 256)])
+def test_c3_with_256_byte_aligned_slices(xcd, wg):
     """The uneven batch as the benchmark codes it: every slice pitch rounded
     up to 256 bytes (blocks random over their whole memory, so B = w * S),
     the split-K grid executor in both item orders."""
@@ -209,7 +209,7 @@ def test_c3_with_256_byte_aligned_slices(xcd):
     plans = PlanCache()
     arena = Arena(sum(stripe_bytes_needed(s) for s in stripes) + 4096)
     bufs, items = _build(stripes, plans, arena)
-    b = P.Batch(items, mode="grid", wg_threads=128, split_k=2, xcd_order=xcd, launch="direct")
+    b = P.Batch(items, mode="grid", wg_threads=wg, split_k=2, xcd_order=xcd, launch="direct")
     _clear_outputs(bufs, 0x3C)
     b.run()
     sync()
@@ -235,8 +235,8 @@ def test_c1_code_64_stripes_one_launch():
         b.close()
 
 
-@pytest.mark.parametrize("split", [1, 2])
-def test_every_ring_in_one_batch(split):
+@pytest.mark.parametrize("split,wg", [(1, 128), (2, 128), (2, 256)])
+def test_every_ring_in_one_batch(split, wg):
     """All five rings (both degree-8 factors of x^17+1 and the ESP ring
     x^6+x^3+1 included), encodes and decodes, uneven sizes, one launch."""
     rings = [(4, 5, 0x1F), (8, 17, 0x139), (8, 17, 0x1D7), (10, 11, 0x7FF), (6, 9, 0x49)]
@@ -250,7 +250,7 @@ def test_every_ring_in_one_batch(split):
     arena = Arena(sum(stripe_bytes_needed(s) for s in stripes) + 4096)
     bufs, items = _build(stripes, plans, arena)
     _clear_outputs(bufs, 0x3C)
-    b = P.Batch(items, mode="grid", wg_threads=128, split_k=split)
+    b = P.Batch(items, mode="grid", wg_threads=wg, split_k=split)
     b.run()
     sync()
     _check_stripes(stripes, bufs, plans, ncols=16)
@@ -310,7 +310,7 @@ def test_batch_errors():
     with pytest.raises(P.PyritError) as e:
         P.Batch([(plan, [], blocks, st.S)], xcd_order=2)
     assert e.value.code == -1
-    for bad_split in [dict(split_k=3), dict(split_k=2, wg_threads=256),
+    for bad_split in [dict(split_k=3), dict(split_k=2, wg_threads=64),
                       dict(split_k=2, mode="queue", wg_threads=128)]:
         with pytest.raises(P.PyritError) as e:
             P.Batch([(plan, [], blocks, st.S)], **bad_split)
