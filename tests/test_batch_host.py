@@ -97,7 +97,7 @@ def test_wide_codes_split_into_passes():
 
 def test_two_split_k_pairs_per_workgroup(c3):
     """256-thread split-K workgroups hold two pairs on adjacent chunks: half
-    as many items as 128-thread ones, and the same bytes."""
+    as many items as 128-thread ones (one pair), and the same bytes."""
     stripes, items = c3
     one = P.batch_describe(items, wg_threads=128, split_k=2)
     two = P.batch_describe(items, wg_threads=256, split_k=2)

@@ -148,10 +148,12 @@ def test_c3_all_4096_uneven_stripes_one_launch(mode, xcd, split):
     _check_stripes(stripes, bufs, plans, ncols=10)
 
 
-def test_c1_full_size_as_benched():
+@pytest.mark.parametrize("wg", [256, 128])
+def test_c1_full_size_as_benched(wg):
     """The headline stripe in the benchmark's own layout and launch: 64 MiB
     blocks, slices 8 MiB + 4 KiB apart, blocks 4352 B apart, the grid
-    executor with 128-thread split-K workgroups, direct dispatch.  Sampled
+    executor with split-K workgroups of two pairs (the benched form) or one
+    pair, direct dispatch.  Sampled
     columns of every parity slice against the oracle; the gaps between
     slices untouched; then the workload's 4-erasure decode the same way."""
     import dataclasses
@@ -166,7 +168,7 @@ def test_c1_full_size_as_benched():
         P.fill_random(blocks[j], st.key(j), nrandom=st.nrandom)
     for b in blocks[st.k:]:
         b.fill_(0xA5)
-    b = P.Batch([(plan, [], blocks, st.S, st.pitch)], mode="grid", wg_threads=128, xcd_order=0,
+    b = P.Batch([(plan, [], blocks, st.S, st.pitch)], mode="grid", wg_threads=wg, xcd_order=0,
                 split_k=2, launch="direct")
     b.run()
     sync()
@@ -184,7 +186,7 @@ def test_c1_full_size_as_benched():
     spare = [pool[(st.k + st.m + q) * stride:(st.k + st.m + q) * stride + st.block_len]
              for q in range(len(er))]
     dec = [spare[er.index(i)] if i in er else blk for i, blk in enumerate(blocks)]
-    d = P.Batch([(plan, er, dec, st.S, st.pitch)], mode="grid", wg_threads=128, split_k=2,
+    d = P.Batch([(plan, er, dec, st.S, st.pitch)], mode="grid", wg_threads=wg, split_k=2,
                 launch="direct")
     d.run()
     sync()
