@@ -135,3 +135,18 @@ def test_describe_errors():
         P.batch_describe([(plan, [0, 1, 2], blocks, S, pitch)])
     assert e.value.code == -6
     assert P.batch_describe([])["work_items"] == 0
+
+
+def test_largest_slice_window():
+    """(w - 1) * pitch + S must stay below 2^31: the largest accepted block
+    ends 64 bytes short of it, one more 64 bytes of pitch is refused."""
+    S = (1 << 28) - 64
+    st = W.Stripe(*W.RING_W8, k=2, m=1, B=8 * S)
+    plan = P.Plan(*W.RING_W8, 2, 1)
+    blocks = [BASE + i * (1 << 32) for i in range(3)]
+    d = P.batch_describe([(plan, [], blocks, S, S + 64)])
+    assert d["moved_bytes"] == 3 * 8 * S and 7 * (S + 64) + S == (1 << 31) - 64
+    with pytest.raises(P.PyritError) as e:
+        P.batch_describe([(plan, [], blocks, S, S + 128)])
+    assert e.value.code == EINVAL
+    assert st.S == S
