@@ -21,7 +21,7 @@
  * Slice t holds coefficient t of every symbol: symbol (o, b), for byte offset
  * o < S and bit b < 8, is sum_t bit b of byte o of slice t, times x^t.  S must
  * be a positive multiple of 64, every block pointer 16-byte aligned, and
- * w * S < 2^31.
+ * (w - 1) * pitch + S < 2^31 (w * S for packed slices).
  *
  * Integers that encode polynomials over GF(2) use bit i for the coefficient
  * of x^i (p includes its x^w term: x^8+x^5+x^4+x^3+1 is 0x139).
@@ -64,7 +64,7 @@ enum {
 
 #define PYRIT_KMAX 64      /* maximum data blocks per stripe */
 #define PYRIT_MMAX 64      /* maximum parity blocks per stripe */
-#define PYRIT_SMAX_TOTAL 0x7fffffffu /* w * S must stay below this */
+#define PYRIT_SMAX_TOTAL 0x7fffffffu /* (w - 1) * pitch + S must stay below this */
 
 /* Text for an error code (static storage). */
 const char *pyrit_strerror(int code);
