@@ -119,7 +119,8 @@ __device__ __forceinline__ void code_item(const AS4 PassDesc *passes, const AS4 
   }
 }
 
-// grid mode: workgroup b codes item b, one chunk per wave.  Items are
+// grid mode: workgroup b codes item b, one chunk per wave (one per split-K
+// pair of waves when KS = 2).  Items are
 // numbered pass by pass, so the workgroup finds its pass by binary search
 // over the per-pass start indices (a small array every workgroup reads, hot
 // in the scalar cache) instead of loading a per-item record.

@@ -127,7 +127,8 @@ int build_batch_image(const pyrit_batch_item *items, int n_items, const pyrit_tu
   const int grid = persistent ? resident_grid : 0;
   const uint32_t total_waves = persistent ? (uint32_t)grid * wpw : 0u;
 
-  // Work items.  grid mode: one item per workgroup, one chunk per wave, the
+  // Work items.  grid mode: one item per workgroup, one chunk per wave (per
+  // split-K pair), the
   // passes in ring order so each ring's workgroups are dispatched together.
   // persistent modes: tiles of several chunks, enough for every wave to take
   // a few, at most 64 KiB of columns.

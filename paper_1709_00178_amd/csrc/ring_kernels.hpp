@@ -231,11 +231,12 @@ __device__ __forceinline__ void load_block(typename Vec<V>::T (&d)[W], const uin
 //   zero lifted coefficients; they are neither reduced nor stored.
 //
 // KS = 1: the wave codes every input block of its column chunk.
-// KS = 2 (split-K): the two waves of a 128-thread workgroup share one column
+// KS = 2 (split-K): a pair of waves of one workgroup shares one column
 // chunk.  Wave `part` codes input blocks part, part + 2, ...; each reduces
 // its partial sums mod p (reduction is linear), wave part keeps outputs
 // r = part, part + 2, ... and hands the other outputs' partial slices to the
-// other wave through LDS (`xch`: MO x W x 64 lane values, one writer each).
+// other wave through LDS (`xch`: MO x W x 64 lane values, one writer each;
+// the workgroup's one barrier sits between the writes and the reads).
 // Half as many columns are in flight for the same number of waves, which
 // shrinks the set of HBM rows open at once (measured on MI355X: 6.6 -> 7.0
 // TB/s for the 10-in/4-out, 8-slice access pattern).
