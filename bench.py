@@ -366,17 +366,19 @@ def bench_c1_stripes(args, stream, out, log):
     from paper_1709_00178_amd import autotune
     from paper_1709_00178_amd import workloads as W
     base = W.c1()
+    # slices 128 KiB + 4 KiB apart, as the C1 stripe's (packed 128 KiB slices
+    # would be a power of two apart)
     stripes = [W.Stripe(base.w, base.n, base.p, k=base.k, m=base.m, B=1 << 20, stripe=i,
-                        seed=base.seed) for i in range(64)]
+                        seed=base.seed, pad=4096) for i in range(64)]
     plan = P.Plan(base.w, base.n, base.p, base.k, base.m)
     arena = Arena(arena_bytes(stripes, BLOCK_SKEW), BLOCK_SKEW)
     bl = [stripe_buffers(st, arena) for st in stripes]
-    batch, cfg, _ = autotune.tuned_batch([(plan, [], b, st.S) for st, b in zip(stripes, bl)],
+    batch, cfg, _ = autotune.tuned_batch([(plan, [], b, st.S, st.pitch) for st, b in zip(stripes, bl)],
                                          stream, log=log)
 
     def plain_all():
         for st, b in zip(stripes, bl):
-            plan.encode(b[:st.k], b[st.k:], st.S, stream=stream)
+            plan.encode(b[:st.k], b[st.k:], st.S, stream=stream, pitch=st.pitch)
 
     plain_all()
     batch.run(stream)
@@ -385,7 +387,7 @@ def bench_c1_stripes(args, stream, out, log):
     moved = sum(st.moved_bytes() for st in stripes)
     user = sum(st.k * st.B for st in stripes)
     out["c1_code_64_stripes"] = {
-        "stripes": len(stripes), "block_bytes": 1 << 20,
+        "stripes": len(stripes), "block_bytes": 1 << 20, "slice_pitch": stripes[0].pitch,
         "plain_64_launches": {"ms": round(p_ms, 4), "GBps_data": round(user / (p_ms * 1e-3) / 1e9, 1),
                               "GBps_moved": round(moved / (p_ms * 1e-3) / 1e9, 1),
                               "frac_of_peak": round(moved / (p_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)},
