@@ -326,8 +326,9 @@ def test_batch_errors():
     sync()
 
 
-@pytest.mark.parametrize("mode,split", [("grid", 1), ("grid", 2), ("queue", 1), ("static", 1)])
-def test_parity_and_embedding_stripes_in_one_batch(mode, split):
+@pytest.mark.parametrize("mode,split,wg", [("grid", 1, 128), ("grid", 2, 128), ("grid", 2, 256),
+                                           ("queue", 1, 128), ("static", 1, 128)])
+def test_parity_and_embedding_stripes_in_one_batch(mode, split, wg):
     """Parity-transform stripes (encodes and decodes) next to embedding ones
     in one launch, each against the oracle's definition of its code."""
     torch = torch_mod()
@@ -353,7 +354,7 @@ def test_parity_and_embedding_stripes_in_one_batch(mode, split):
         keep.append((plan, dev))
         items.append((plan, er, dev, S))
         checks.append((dev, code, outs))
-    b = P.Batch(items, mode=mode, split_k=split)
+    b = P.Batch(items, mode=mode, split_k=split, wg_threads=wg)
     b.run()
     sync()
     for i, (dev, code, outs) in enumerate(checks):
