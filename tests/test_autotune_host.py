@@ -59,3 +59,16 @@ def test_cache_file_round_trip(tmp_path, monkeypatch):
     assert json.loads(path.read_text()) == {"sig": {"mode": "grid", "wg_threads": 256, "split_k": 2}}
     path.write_text("not json")
     assert autotune._load_file() == {}
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus N > 1 exits with a message, before
+    touching any device."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "single GPU" in r.stderr and r.stdout == ""
