@@ -1,5 +1,6 @@
-"""Host side of the autotuner (no GPU needed): batch signatures and the
-cache file.  Every candidate executor is one pyrit_batch_describe accepts."""
+"""Host side of the autotuner and the benchmark (no GPU needed): batch
+signatures, the cache file, every candidate executor being one
+pyrit_batch_describe accepts, and the benchmark's one-GPU rule."""
 import json
 
 import paper_1709_00178_amd as P
