@@ -140,6 +140,34 @@ def test_served_mix_with_256_byte_aligned_slices():
     sv.close()
 
 
+def test_served_mix_with_parity_transform_plans():
+    """Requests over GF(2^4) and GF(2^10) served with parity-transform plans
+    (the paper's other transform, a different code) next to embedding plans
+    over GF(2^8): every request's bytes equal the same plan coding it alone."""
+    trace = small_trace(n=90, seed=17)
+    inputs = serve.InputPool(128 << 20, key=0xD00D)
+    plans = {}
+    for rq in trace:
+        st = rq.stripe
+        key = (st.w, st.n, st.p, st.k, st.m)
+        if key not in plans and st.w in (4, 10):
+            plans[key] = P.Plan(*key, transform="parity")
+    assert plans
+    prep = serve.prepare(trace, inputs, plans)
+    sv = serve.Server(pool_bytes=1 << 30, slots=2, release_outputs=False)
+    res, stats = sv.run(prep.array)
+    n_parity = 0
+    for i, (st, offs, large) in enumerate(prep.meta):
+        plan = plans[(st.w, st.n, st.p, st.k, st.m)]
+        n_parity += plan.transform == "parity"
+        alone, _ = _alone(plan, st, inputs, offs)
+        for q, blk in enumerate(alone):
+            mixed = _pool_view(sv, int(res[i]["out_offset"] + q * res[i]["out_stride"]), st.block_len)
+            assert np.array_equal(mixed[:st.block_len], blk), (i, q, st)
+    assert n_parity > len(trace) // 3
+    sv.close()
+
+
 def test_per_request_mode_same_bytes():
     trace = small_trace(n=60, seed=11)
     inputs = serve.InputPool(64 << 20, key=0xBEEF)
