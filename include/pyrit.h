@@ -296,7 +296,9 @@ typedef struct pyrit_batch pyrit_batch;
  * pointer tables to device memory (one allocation owned by the batch) and
  * instantiate the hipGraph.  Nothing runs on the GPU yet.  tune may be NULL.
  * Items are validated like pyrit_encode / pyrit_decode; the first failing
- * item's code is returned and no batch is created.  The items of one batch
+ * item's code is returned and no batch is created.  A batch whose launch
+ * would exceed 2^32 - 1 threads (grid mode: one workgroup per work item) is
+ * PYRIT_EINVAL; split it into several batches.  The items of one batch
  * run concurrently: no item may write a block (or slice bytes) that another
  * item of the same batch reads or writes. */
 int pyrit_batch_create(const pyrit_batch_item *items, int n_items, const pyrit_tune *tune,

@@ -268,7 +268,10 @@ int build_batch_image(const pyrit_batch_item *items, int n_items, const pyrit_tu
   bi->wg = t.wg_threads;
   bi->xcd_order = t.xcd_order;
   bi->split = t.split_k;
-  bi->grid = persistent ? grid : t.xcd_order ? (int)(kXcds * longest) : (int)work.size();
+  // The dispatch packet counts the grid in threads, in 32 bits.
+  const uint64_t wgs = persistent ? (uint64_t)grid : t.xcd_order ? (uint64_t)kXcds * longest : work.size();
+  if (wgs * (uint64_t)t.wg_threads > 0xFFFFFFFFull) return PYRIT_EINVAL;
+  bi->grid = (int)wgs;
   return PYRIT_OK;
 }
 

@@ -150,3 +150,19 @@ def test_largest_slice_window():
         P.batch_describe([(plan, [], blocks, S, S + 128)])
     assert e.value.code == EINVAL
     assert st.S == S
+
+
+def test_grid_of_more_than_2_32_threads_is_refused():
+    """Grid mode launches one workgroup per work item and the dispatch counts
+    threads in 32 bits: 32 stripes of 2^28-byte slice windows at 512 column
+    bytes per 256-thread workgroup make 2^24 workgroups, 2^32 threads, one
+    too many; 31 stripes fit."""
+    S = (1 << 28) - 64
+    plan = P.Plan(*W.RING_W8, 2, 1)
+    items = [(plan, [], [BASE + (3 * s + i) * (1 << 32) for i in range(3)], S, S)
+             for s in range(32)]
+    with pytest.raises(P.PyritError) as e:
+        P.batch_describe(items, wg_threads=256, split_k=2)
+    assert e.value.code == EINVAL
+    d = P.batch_describe(items[:31], wg_threads=256, split_k=2)
+    assert d["grid"] == d["work_items"] == 31 << 19
