@@ -87,14 +87,27 @@ def cauchy_light(w: int, n: int, p: int, k: int, m: int):
     return G, rs, cs, wt.value
 
 
-def _dev_ptr(x) -> int:
+def _dev_ptr(x, need: int = 0) -> int:
+    """Device address of a tensor (or a plain integer address, taken as is).
+    A tensor must be a contiguous device tensor of at least ``need`` bytes:
+    the kernels address a buffer as flat bytes from its first element."""
     if isinstance(x, int):
         return x
     if hasattr(x, "data_ptr"):
         if not x.is_cuda:
             raise ValueError("block buffers must be device tensors")
+        if not x.is_contiguous():
+            raise ValueError("device buffers must be contiguous")
+        have = x.numel() * x.element_size()
+        if have < need:
+            raise ValueError(f"device buffer holds {have} bytes, {need} needed")
         return int(x.data_ptr())
     raise TypeError(f"expected a device tensor or a pointer, got {type(x)}")
+
+
+def _block_bytes(w: int, S: int, pitch: int) -> int:
+    """Bytes a block of w slices of S bytes at a stride of pitch spans."""
+    return (w - 1) * (pitch or S) + S
 
 
 def _stream_handle(stream) -> int | None:
@@ -106,10 +119,10 @@ def _stream_handle(stream) -> int | None:
     return int(stream.cuda_stream) or None
 
 
-def _ptr_array(xs):
+def _ptr_array(xs, need: int = 0):
     arr = (ctypes.c_void_p * max(1, len(xs)))()
     for i, x in enumerate(xs):
-        arr[i] = _dev_ptr(x) if x is not None else None
+        arr[i] = _dev_ptr(x, need) if x is not None else None
     return arr
 
 
@@ -181,15 +194,17 @@ class Plan:
         at a stride of ``pitch`` bytes (0: packed, pitch = S)."""
         if len(data) != self.k or len(parity) != self.m:
             raise ValueError("need k data and m parity buffers")
-        _check(lib().pyrit_encode_ex(self._h, _ptr_array(data), _ptr_array(parity), S, pitch,
-                                     vec_bytes, _stream_handle(stream)))
+        need = _block_bytes(self.w, S, pitch)
+        _check(lib().pyrit_encode_ex(self._h, _ptr_array(data, need), _ptr_array(parity, need), S,
+                                     pitch, vec_bytes, _stream_handle(stream)))
 
     def decode(self, erased, blocks, S: int, stream=None, pitch: int = 0) -> None:
         """Rewrite the erased entries of ``blocks`` (k + m buffers)."""
         if len(blocks) != self.k + self.m:
             raise ValueError("need k + m block buffers")
         er = (ctypes.c_int * max(1, len(erased)))(*erased)
-        _check(lib().pyrit_decode_ex(self._h, er, len(erased), _ptr_array(blocks), S, pitch,
+        _check(lib().pyrit_decode_ex(self._h, er, len(erased),
+                                     _ptr_array(blocks, _block_bytes(self.w, S, pitch)), S, pitch,
                                      _stream_handle(stream)))
 
 
@@ -204,7 +219,7 @@ def _batch_items(items):
         if len(blocks) != plan.k + plan.m:
             raise ValueError("each item needs k + m block entries")
         er = (ctypes.c_int * max(1, len(erased)))(*erased)
-        bl = _ptr_array(blocks)
+        bl = _ptr_array(blocks, _block_bytes(plan.w, S, pitch))
         keep += [er, bl, plan]
         arr[i].plan = plan._h
         arr[i].n_erased = len(erased)
@@ -306,14 +321,15 @@ def fill_random(buf, key: int, nrandom: int | None = None, nbytes: int | None = 
         nbytes = buf.numel() * buf.element_size()
     if nrandom is None:
         nrandom = nbytes
-    _check(lib().pyrit_fill_random(_dev_ptr(buf), nbytes, nrandom, key & ((1 << 64) - 1),
+    _check(lib().pyrit_fill_random(_dev_ptr(buf, nbytes), nbytes, nrandom, key & ((1 << 64) - 1),
                                    _stream_handle(stream)))
 
 
 def copy(dst, src, nbytes: int | None = None, stream=None) -> None:
     if nbytes is None:
         nbytes = src.numel() * src.element_size()
-    _check(lib().pyrit_copy(_dev_ptr(dst), _dev_ptr(src), nbytes, _stream_handle(stream)))
+    _check(lib().pyrit_copy(_dev_ptr(dst, nbytes), _dev_ptr(src, nbytes), nbytes,
+                            _stream_handle(stream)))
 
 
 def to_sliced(w: int, symbols, sliced, n_symbols: int | None = None, pitch: int = 0,
@@ -322,7 +338,9 @@ def to_sliced(w: int, symbols, sliced, n_symbols: int | None = None, pitch: int 
     for larger w) -> bit-sliced block of w slices (see pyrit_to_sliced)."""
     if n_symbols is None:
         n_symbols = symbols.numel() * symbols.element_size() // (1 if w <= 8 else 2)
-    _check(lib().pyrit_to_sliced(w, _dev_ptr(symbols), n_symbols, _dev_ptr(sliced), pitch,
+    sym_bytes = n_symbols * (1 if w <= 8 else 2)
+    _check(lib().pyrit_to_sliced(w, _dev_ptr(symbols, sym_bytes), n_symbols,
+                                 _dev_ptr(sliced, _block_bytes(w, n_symbols // 8, pitch)), pitch,
                                  _stream_handle(stream)))
 
 
@@ -331,5 +349,7 @@ def from_sliced(w: int, sliced, symbols, n_symbols: int | None = None, pitch: in
     """Bit-sliced block -> symbol-major block (inverse of `to_sliced`)."""
     if n_symbols is None:
         n_symbols = symbols.numel() * symbols.element_size() // (1 if w <= 8 else 2)
-    _check(lib().pyrit_from_sliced(w, _dev_ptr(sliced), pitch, n_symbols, _dev_ptr(symbols),
+    sym_bytes = n_symbols * (1 if w <= 8 else 2)
+    _check(lib().pyrit_from_sliced(w, _dev_ptr(sliced, _block_bytes(w, n_symbols // 8, pitch)),
+                                   pitch, n_symbols, _dev_ptr(symbols, sym_bytes),
                                    _stream_handle(stream)))

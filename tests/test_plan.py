@@ -345,3 +345,46 @@ def test_decode_matrix_cache_under_threads():
         assert list(surv) == list(s2) and np.array_equal(D, D2), er
     for er, (s, D) in ref.items():
         assert np.array_equal(D, fresh.decode_matrix(list(er))[1])
+
+
+class _FakeDeviceTensor:
+    """Just enough of a device tensor for the binding's argument checks."""
+
+    def __init__(self, nbytes, contiguous=True, cuda=True):
+        self.nbytes, self.contiguous, self.is_cuda = nbytes, contiguous, cuda
+
+    def data_ptr(self):
+        return 1 << 36
+
+    def is_contiguous(self):
+        return self.contiguous
+
+    def numel(self):
+        return self.nbytes
+
+    def element_size(self):
+        return 1
+
+
+def test_binding_refuses_short_or_strided_buffers():
+    """The kernels address a block as (w - 1) * pitch + S flat bytes from its
+    first element: the binding refuses, before any library call, a tensor
+    that holds fewer bytes, a non-contiguous one and a host one."""
+    plan = P.Plan(*W.RING_W8, 2, 1)
+    S, pitch = 4096, 8192
+    need = 7 * pitch + S
+    ok = [_FakeDeviceTensor(need) for _ in range(2)]
+    for bad, what in [(_FakeDeviceTensor(need - 1), "needed"),
+                      (_FakeDeviceTensor(need, contiguous=False), "contiguous"),
+                      (_FakeDeviceTensor(need, cuda=False), "device tensors")]:
+        with pytest.raises(ValueError, match=what):
+            plan.encode(ok, [bad], S, pitch=pitch)
+        with pytest.raises(ValueError, match=what):
+            plan.decode([0], [bad] + ok, S, pitch=pitch)
+        with pytest.raises(ValueError, match=what):
+            P.batch_describe([(plan, [], ok + [bad], S, pitch)])
+    assert P._block_bytes(8, S, 0) == 8 * S
+    with pytest.raises(ValueError, match="needed"):
+        P.to_sliced(8, _FakeDeviceTensor(4096), _FakeDeviceTensor(4096 - 1), n_symbols=4096)
+    with pytest.raises(ValueError, match="needed"):
+        P.from_sliced(10, _FakeDeviceTensor(5120), _FakeDeviceTensor(8191), n_symbols=4096)
