@@ -119,10 +119,23 @@ def _stream_handle(stream) -> int | None:
     return int(stream.cuda_stream) or None
 
 
-def _ptr_array(xs, need: int = 0):
+def _coded_blocks(k: int, m: int, erased) -> set:
+    """Ids of the blocks a call reads or writes: all k + m for an encode; for
+    a decode the first k survivors and the erased blocks (other entries are
+    never touched)."""
+    if not erased:
+        return set(range(k + m))
+    er = set(erased)
+    return set([b for b in range(k + m) if b not in er][:k]) | er
+
+
+def _ptr_array(xs, need: int = 0, used=None):
+    """C array of device addresses; entries in ``used`` (default: all) must
+    hold ``need`` bytes."""
     arr = (ctypes.c_void_p * max(1, len(xs)))()
     for i, x in enumerate(xs):
-        arr[i] = _dev_ptr(x, need) if x is not None else None
+        n = need if used is None or i in used else 0
+        arr[i] = _dev_ptr(x, n) if x is not None else None
     return arr
 
 
@@ -204,7 +217,8 @@ class Plan:
             raise ValueError("need k + m block buffers")
         er = (ctypes.c_int * max(1, len(erased)))(*erased)
         _check(lib().pyrit_decode_ex(self._h, er, len(erased),
-                                     _ptr_array(blocks, _block_bytes(self.w, S, pitch)), S, pitch,
+                                     _ptr_array(blocks, _block_bytes(self.w, S, pitch),
+                                                _coded_blocks(self.k, self.m, erased)), S, pitch,
                                      _stream_handle(stream)))
 
 
@@ -219,7 +233,8 @@ def _batch_items(items):
         if len(blocks) != plan.k + plan.m:
             raise ValueError("each item needs k + m block entries")
         er = (ctypes.c_int * max(1, len(erased)))(*erased)
-        bl = _ptr_array(blocks, _block_bytes(plan.w, S, pitch))
+        bl = _ptr_array(blocks, _block_bytes(plan.w, S, pitch),
+                        _coded_blocks(plan.k, plan.m, erased))
         keep += [er, bl, plan]
         arr[i].plan = plan._h
         arr[i].n_erased = len(erased)

@@ -384,6 +384,17 @@ def test_binding_refuses_short_or_strided_buffers():
         with pytest.raises(ValueError, match=what):
             P.batch_describe([(plan, [], ok + [bad], S, pitch)])
     assert P._block_bytes(8, S, 0) == 8 * S
+    # a decode touches only the first k survivors and the erased blocks:
+    # block 2 (a survivor past the first k) may be any buffer
+    stub = _FakeDeviceTensor(64)
+    assert P._coded_blocks(2, 1, [0]) == {0, 1, 2}
+    assert P._coded_blocks(2, 2, [1]) == {0, 1, 2}
+    assert P._coded_blocks(2, 2, []) == {0, 1, 2, 3}
+    plan4 = P.Plan(*W.RING_W8, 2, 2)
+    d = P.batch_describe([(plan4, [1], [ok[0], ok[1], _FakeDeviceTensor(need), stub], S, pitch)])
+    assert d["moved_bytes"] == 3 * 8 * S
+    with pytest.raises(ValueError, match="needed"):
+        P.batch_describe([(plan4, [1], [ok[0], ok[1], stub, stub], S, pitch)])
     with pytest.raises(ValueError, match="needed"):
         P.to_sliced(8, _FakeDeviceTensor(4096), _FakeDeviceTensor(4096 - 1), n_symbols=4096)
     with pytest.raises(ValueError, match="needed"):
