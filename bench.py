@@ -434,29 +434,50 @@ def bench_layout(args, stream, out, log):
     torch.cuda.empty_cache()
 
 
+# Outputs per pass of the plain kernel for the rings with n <= 9 (the AOP
+# ring of GF(2^4) and the ESP ring of GF(2^6)): every further pass re-reads
+# the k data blocks.
+PLAIN_OUTPUTS_PER_PASS_N9 = 8
+
+
 def bench_paper_shapes(args, stream, out, log):
     """The code shapes of the paper's Sec. IV figures, (12,8) over GF(2^4) and
-    (60,40), (60,20) over GF(2^6), with 1 MiB blocks, under the embedding and
-    the parity transform (one plain encode per call; passes of at most four
-    parity blocks each re-read the data blocks)."""
+    (60,40), (60,20) over GF(2^6), under the embedding and the parity
+    transform (one plain encode per call; passes of at most eight parity
+    blocks each re-read the data blocks).  At the figures' 1 MiB blocks a
+    launch is a few hundred workgroups and cannot fill the GPU; blocks of
+    about 16 MiB (w slices of S bytes at a pitch of S + 4 KiB) show the same kernels against the HBM
+    roofline, moved bytes counting every pass's re-read of the data."""
     import torch
 
     import paper_1709_00178_amd as P
     from paper_1709_00178_amd import workloads as W
     res = {}
     for (w, n, p), k, m in (((4, 5, 0x1F), 8, 4), ((6, 9, 0x49), 40, 20), ((6, 9, 0x49), 20, 40)):
-        st = W.Stripe(w, n, p, k=k, m=m, B=1 << 20, seed=W.BASE_SEED + 9)
-        arena = Arena(arena_bytes([st], BLOCK_SKEW), BLOCK_SKEW)
-        bl = stripe_buffers(st, arena)
-        row = {"w": w, "k": k, "m": m, "block_bytes": st.B}
-        for tr in ("embedding", "parity"):
-            plan = P.Plan(w, n, p, k, m, transform=tr)
-            fn = lambda: plan.encode(bl[:k], bl[k:], st.S, stream=stream)
-            fn()
-            ms = min(batch_time_ms(fn, 10, stream) for _ in range(2))
-            row[tr] = {"GBps_data": round(k * st.B / (ms * 1e-3) / 1e9, 1), "ms": round(ms, 4)}
+        row = {"w": w, "k": k, "m": m}
+        # a padded layout holds whole slices: the large block is w * S bytes
+        for B, pad in ((1 << 20, 0), (w * W.slice_bytes(16 << 20, w), 4096)):
+            st = W.Stripe(w, n, p, k=k, m=m, B=B, seed=W.BASE_SEED + 9, pad=pad)
+            arena = Arena(arena_bytes([st], BLOCK_SKEW), BLOCK_SKEW)
+            bl = stripe_buffers(st, arena)
+            passes = -(-m // PLAIN_OUTPUTS_PER_PASS_N9)
+            moved = (passes * k + m) * w * st.S
+            into = row if B == 1 << 20 else row.setdefault("blocks_16MiB", {"block_bytes": B})
+            if B == 1 << 20:
+                row["block_bytes"] = B
+            for tr in ("embedding", "parity"):
+                plan = P.Plan(w, n, p, k, m, transform=tr)
+                fn = lambda: plan.encode(bl[:k], bl[k:], st.S, stream=stream, pitch=st.pitch)
+                fn()
+                ms = min(batch_time_ms(fn, 10, stream) for _ in range(2))
+                r = {"GBps_data": round(k * B / (ms * 1e-3) / 1e9, 1), "ms": round(ms, 4)}
+                if B != 1 << 20:
+                    r["GBps_moved"] = round(moved / (ms * 1e-3) / 1e9, 1)
+                    r["frac_of_peak"] = round(moved / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
+                into[tr] = r
+            del arena, bl
+            torch.cuda.empty_cache()
         res[f"({k + m},{k}) GF(2^{w})"] = row
-        del arena, bl
     out["paper_code_shapes"] = res
     torch.cuda.empty_cache()
 

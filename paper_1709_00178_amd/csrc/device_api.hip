@@ -11,12 +11,21 @@ template <int RING>
 int launch_plain_ring(int nout, int vec_bytes, const PassArgs &a, hipStream_t st);
 
 int default_vec_bytes(int ring, int nout) {
-  // Widest column whose accumulators (nout * n * V dwords per lane) stay
-  // within 80 registers, keeping at least four waves per SIMD.
+  // Column bytes per lane of the plain kernel, chosen by measurement on
+  // MI355X (encodes of 16 MiB blocks, every ring and output count against
+  // 4-, 8- and 16-byte lanes): the 8-slice field takes 4-byte lanes at every
+  // output count (16-byte lanes lost up to 13%); the 4-slice field 8-byte
+  // lanes up to four outputs (16-byte lanes lost up to 35%); the 6- and
+  // 10-slice fields 16-byte lanes for one output, 8-byte lanes up to four and
+  // 4-byte lanes beyond (8-byte lanes also gave C2's 256 launches of 4 MiB
+  // blocks +6% over 4-byte ones).  The widest lane that fits a register
+  // budget is not the fastest: at the same accumulator count, 6-slice codes
+  // ran 11% faster with four outputs on 8-byte lanes than with two outputs on
+  // 16-byte lanes.
   const int n = kRings[ring].n;
-  for (int v : {4, 2, 1})
-    if (nout * n * v <= 80) return 4 * v;
-  return 4;
+  if (n >= 17) return 4;
+  if (n <= 5) return nout <= 4 ? 8 : 4;
+  return nout == 1 ? 16 : nout <= 4 ? 8 : 4;
 }
 
 int launch_pass(int ring, int nout, int vec_bytes, const PassArgs &a, void *stream) {
