@@ -123,6 +123,21 @@ def arena_bytes(stripes, skew=0):
     return tot + 4096
 
 
+def host_cpu():
+    """The host CPU the oracle baseline ran on: model name and the logical
+    CPUs this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus_usable": len(os.sched_getaffinity(0))}
+
+
 def cpu_baseline(target_s: float = 10.0):
     """The CPU oracle encoding a column sample of the same code on all host
     cores (the oracle as written: plain log/antilog tables, OpenMP)."""
@@ -159,7 +174,8 @@ def cpu_baseline(target_s: float = 10.0):
     return {"value": round(gbps, 4), "unit": "GB/s", "cores": nt, "kind": "oracle",
             "sample": f"GF(2^8) k=10 m=4 Cauchy encode of a {Sp >> 20} MiB column sample of every "
                       f"slice ({st.k * st.w * Sp / 1e6:.0f} MB of data) x {reps} passes, {el:.1f} s",
-            "single_thread_GBps": round(st.k * st.w * S1 * reps1 / el1 / 1e9, 4)}
+            "single_thread_GBps": round(st.k * st.w * S1 * reps1 / el1 / 1e9, 4),
+            "host_cpu": host_cpu()}
 
 
 # Executor of the C1 batch: grid mode, 256-thread workgroups of two split-K

@@ -73,3 +73,10 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "single GPU" in r.stderr and r.stdout == ""
+
+
+def test_bench_records_the_host_cpu():
+    import bench
+    h = bench.host_cpu()
+    assert h["logical_cpus_usable"] >= 1
+    assert h["model"] is None or isinstance(h["model"], str)
