@@ -3,8 +3,9 @@
 For a batch it times a small set of executors (queue drain mode, threads per
 workgroup, split-K, tile width, XCD-contiguous item order) in both launch forms (hipGraph
 replay and direct dispatch) with HIP events on the caller's stream and keeps
-the fastest.  Results are cached per batch signature (rings, code shapes, slice
-size class, encode/decode mix) in memory and in a JSON file
+the fastest.  Results are cached per batch signature (rings, k and output
+ranges, slice-size class, decode share, stripe-count class, slice alignment)
+in memory and in a JSON file
 (``PYRIT_AUTOTUNE_CACHE``, default ``~/.cache/pyrit_mi355x_autotune.json``),
 so a signature is only tuned once per machine.
 
