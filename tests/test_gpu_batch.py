@@ -110,14 +110,17 @@ def test_batch_graph_replays_with_eager_work_between(mode):
         _check_stripes(stripes, bufs, plans, ncols=8, seed=rep)
 
 
-@pytest.mark.parametrize("mode,xcd,split", [("grid", 0, 1), ("grid", 1, 1), ("grid", 1, 2),
-                                            ("queue", 0, 1), ("static", 0, 1)])
-def test_c2_all_stripes_one_launch(mode, xcd, split):
+@pytest.mark.parametrize("mode,xcd,split,wg", [("grid", 0, 1, 0), ("grid", 1, 1, 0), ("grid", 1, 2, 0),
+                                               ("grid", 1, 2, 256), ("grid", 0, 2, 256),
+                                               ("queue", 0, 1, 0), ("static", 0, 1, 0)])
+def test_c2_all_stripes_one_launch(mode, xcd, split, wg):
+    """All 256 stripes in one launch, including the executors the autotuner
+    picks for them (256-thread workgroups of two split-K pairs)."""
     stripes = W.c2()
     plans = PlanCache()
     arena = Arena(sum(stripe_bytes_needed(s) for s in stripes) + 4096)
     bufs, items = _build(stripes, plans, arena)
-    b = P.Batch(items, mode=mode, xcd_order=xcd, split_k=split)
+    b = P.Batch(items, mode=mode, xcd_order=xcd, split_k=split, wg_threads=wg)
     info = b.info()
     assert info["passes"] == 256
     assert info["moved_bytes"] == sum(s.moved_bytes() for s in stripes)
@@ -126,20 +129,23 @@ def test_c2_all_stripes_one_launch(mode, xcd, split):
     _check_stripes(stripes, bufs, plans, ncols=12)
 
 
-@pytest.mark.parametrize("mode,xcd,split", [("grid", 0, 1), ("grid", 1, 1), ("grid", 0, 2),
-                                            ("grid", 1, 2), ("queue", 0, 1), ("static", 0, 1)])
-def test_c3_all_4096_uneven_stripes_one_launch(mode, xcd, split):
+@pytest.mark.parametrize("mode,xcd,split,wg", [("grid", 0, 1, 0), ("grid", 1, 1, 0), ("grid", 0, 2, 0),
+                                               ("grid", 1, 2, 0), ("grid", 1, 2, 256),
+                                               ("grid", 1, 1, 64), ("queue", 0, 1, 0),
+                                               ("static", 0, 1, 0)])
+def test_c3_all_4096_uneven_stripes_one_launch(mode, xcd, split, wg):
     """The uneven batch: w in {4,8,10}, k in [4,16], m in [2,4], 4 KiB..4 MiB
-    blocks, 30% decodes, all in one launch."""
+    blocks, 30% decodes, all in one launch (also with the 256- and 64-thread
+    executors the autotuner has picked for it)."""
     stripes = W.c3()
     plans = PlanCache()
     arena = Arena(sum(stripe_bytes_needed(s) for s in stripes) + 4096)
     bufs, items = _build(stripes, plans, arena)
-    b = P.Batch(items, mode=mode, xcd_order=xcd, split_k=split)
+    b = P.Batch(items, mode=mode, xcd_order=xcd, split_k=split, wg_threads=wg)
     info = b.info()
     assert info["moved_bytes"] == sum(s.moved_bytes() for s in stripes)
     if mode == "grid":  # the host-only description sets up the same launch
-        d = P.batch_describe(items, mode=mode, xcd_order=xcd, split_k=split)
+        d = P.batch_describe(items, mode=mode, xcd_order=xcd, split_k=split, wg_threads=wg)
         assert [d[f] for f in ("passes", "work_items", "moved_bytes", "grid")] == \
                [info[f] for f in ("passes", "work_items", "moved_bytes", "grid")]
     _clear_outputs(bufs, 0x77)
