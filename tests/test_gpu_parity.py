@@ -357,6 +357,42 @@ def test_slice_pitch_plain_and_batched(w, n, p, pad):
     del torch
 
 
+def test_largest_code_the_abi_accepts():
+    """k = m = 64 (PYRIT_KMAX, PYRIT_MMAX) over GF(2^8), ragged slices: the
+    plain encode (16 passes of four outputs, each re-reading the 64 data
+    blocks) against the oracle, the same code in one batch launch, and a
+    decode of all 64 data blocks from the 64 parity blocks."""
+    torch = torch_mod()
+    w, n, p, k, m = 8, 17, 0x139, 64, 64
+    st = W.Stripe(w, n, p, k=k, m=m, B=w * 64 * 41, seed=71)
+    assert st.S == 64 * 41
+    plan = P.Plan(w, n, p, k, m)
+    data = [dev_block(st, j) for j in range(k)]
+    par = [dev_empty(st.block_len) for _ in range(m)]
+    plan.encode(data, par, st.S)
+    sync()
+    want = oracle.Field(w, p).encode(plan.G, W.host_blocks(st), st.S, nthreads=4)
+    for i in range(m):
+        assert np.array_equal(to_host(par[i]), want[i]), i
+    par2 = [dev_empty(st.block_len) for _ in range(m)]
+    b = P.Batch([(plan, [], data + par2, st.S)], mode="grid", wg_threads=256, split_k=2)
+    assert b.info()["passes"] == 16
+    b.launch_direct()
+    sync()
+    for i in range(m):
+        assert torch.equal(par2[i], par[i]), i
+    saved = [d.clone() for d in data]
+    for d in data:
+        d.fill_(0)
+    plan.decode(list(range(k)), data + par, st.S)
+    sync()
+    for j in range(k):
+        assert torch.equal(data[j], saved[j]), j
+    with pytest.raises(P.PyritError) as e:
+        P.Plan(w, n, p, k + 1, 1)
+    assert e.value.code == -1
+
+
 def test_largest_block_the_abi_accepts():
     """A block whose slices reach the end of the 31-bit slice window: S just
     under 256 MiB at a pitch of S + 64, so (w - 1) * pitch + S = 2^31 - 64.
