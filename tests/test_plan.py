@@ -399,3 +399,32 @@ def test_binding_refuses_short_or_strided_buffers():
         P.to_sliced(8, _FakeDeviceTensor(4096), _FakeDeviceTensor(4096 - 1), n_symbols=4096)
     with pytest.raises(ValueError, match="needed"):
         P.from_sliced(10, _FakeDeviceTensor(5120), _FakeDeviceTensor(8191), n_symbols=4096)
+
+
+def test_device_calls_refuse_bad_arguments_before_any_device_work():
+    """Encode and decode check every argument on the host before they touch
+    the device, so the refusals can be pinned without a GPU: the addresses
+    below are never dereferenced and no stream is used."""
+    plan = P.Plan(*W.RING_W8, 2, 2)
+    A, GiB = 1 << 36, 1 << 30
+    d, p = [A, A + GiB], [A + 2 * GiB, A + 3 * GiB]
+    EINVAL, ETOOMANY, EALIGN, EUNSUPPORTED = -1, -6, -8, -9
+    cases = [
+        (lambda: plan.encode(d, p, 0, stream=0), EALIGN),                  # empty slices
+        (lambda: plan.encode(d, p, 100, stream=0), EALIGN),                # S not a multiple of 64
+        (lambda: plan.encode(d, p, 4096, stream=0, pitch=4032), EINVAL),   # pitch below S
+        (lambda: plan.encode(d, p, 4096, stream=0, pitch=4128), EALIGN),   # pitch not a multiple of 64
+        (lambda: plan.encode(d, p, 1 << 28, stream=0, pitch=(1 << 28) + (1 << 26)), EINVAL),  # 2^31 window
+        (lambda: plan.encode([A + 8, A + GiB], p, 4096, stream=0), EALIGN),  # pointer not 16-byte aligned
+        (lambda: plan.encode([None, A + GiB], p, 4096, stream=0), EINVAL),   # missing input
+        (lambda: plan.encode(d, p, 4096, stream=0, vec_bytes=12), EINVAL),
+        (lambda: plan.decode([0, 0], d + p, 4096, stream=0), EINVAL),      # repeated erasure
+        (lambda: plan.decode([4], d + p, 4096, stream=0), EINVAL),         # id past k + m
+        (lambda: plan.decode([-1], d + p, 4096, stream=0), EINVAL),
+        (lambda: plan.decode([0, 1, 2], d + p, 4096, stream=0), ETOOMANY),
+        (lambda: P.Plan(3, 7, 0xB, 2, 1).encode(d, [A + 2 * GiB], 4096, stream=0), EUNSUPPORTED),
+    ]
+    for i, (call, code) in enumerate(cases):
+        with pytest.raises(P.PyritError) as e:
+            call()
+        assert e.value.code == code, i
