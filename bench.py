@@ -651,8 +651,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported. Stripes (or "
-              "column ranges of one stripe) shard across GPUs with no exchange, but this "
-              "build runs and reports a single GPU only.", file=sys.stderr)
+              "column ranges of one stripe) shard across GPUs with no exchange, but the "
+              "benchmark runs and reports a single GPU only.", file=sys.stderr)
         sys.exit(2)
 
     import torch
