@@ -1,8 +1,9 @@
-"""The host plan (ring checks, lifts, plans of both transforms, decoding
-matrices and their cache, the light Cauchy search, error paths) built with
-g++ under AddressSanitizer and UndefinedBehaviorSanitizer and driven by
-tests/native/plan_check.cpp.  CPU only: the plan code is plain C++ and
-compiles without hipcc."""
+"""Host code built with g++ under AddressSanitizer and
+UndefinedBehaviorSanitizer: the plan (ring checks, lifts, plans of both
+transforms, decoding matrices and their cache, the light Cauchy search,
+error paths; driven by tests/native/plan_check.cpp) and the batch builder
+(driven by tests/native/batch_check.cpp).  CPU only: neither needs hipcc or a
+GPU."""
 import os
 import shutil
 import subprocess
@@ -20,6 +21,34 @@ def test_host_plan_under_sanitizers(tmp_path):
              "-I" + os.path.join(ROOT, "include"),
              os.path.join(ROOT, "paper_1709_00178_amd", "csrc", "plan.cpp"),
              os.path.join(ROOT, "tests", "native", "plan_check.cpp"), "-o", str(exe)]
+    r = subprocess.run(build, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-4000:]
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:verify_asan_link_order=0",
+               UBSAN_OPTIONS="print_stacktrace=1")
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300, env=env)
+    assert r.returncode == 0 and r.stdout.strip() == "ok", (r.stdout + r.stderr)[-4000:]
+
+
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+
+
+@pytest.mark.skipif(shutil.which("g++") is None or not os.path.exists(os.path.join(ROCM, "lib", "libamdhip64.so")),
+                    reason="g++ or the HIP runtime library not installed")
+def test_batch_builder_under_sanitizers(tmp_path):
+    """pyrit_batch_describe on seeded random mixed batches (every kernel ring,
+    both transforms, encodes and decodes, ragged and padded slices) with every
+    executor, driven by tests/native/batch_check.cpp: passes and bytes moved
+    against their closed forms, XCD ranges adding up, grid sizes; the
+    builder's host code under AddressSanitizer and UndefinedBehaviorSanitizer.
+    The HIP runtime is linked for its symbols only: nothing calls the device."""
+    exe = tmp_path / "batch_check"
+    csrc = os.path.join(ROOT, "paper_1709_00178_amd", "csrc")
+    build = ["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined",
+             "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-pthread",
+             "-D__HIP_PLATFORM_AMD__", f"-I{ROCM}/include", "-I" + os.path.join(ROOT, "include"),
+             os.path.join(csrc, "batch_host.cpp"), os.path.join(csrc, "plan.cpp"),
+             os.path.join(ROOT, "tests", "native", "batch_check.cpp"),
+             f"-L{ROCM}/lib", "-lamdhip64", f"-Wl,-rpath,{ROCM}/lib", "-o", str(exe)]
     r = subprocess.run(build, capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stderr[-4000:]
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:verify_asan_link_order=0",
