@@ -204,7 +204,10 @@ int pyrit_decode(const pyrit_plan *plan, const int *erased, int n_erased,
  *     128-byte boundaries (block and P multiples of 128) keep every wave
  *     access within whole 128-byte cache lines: a batch of mixed slice sizes
  *     measured 5% faster than with 64-byte aligned packed slices.
- *   vec_bytes: column bytes per lane (4, 8 or 16; 0 = library choice). */
+ *   vec_bytes: column bytes per lane (4, 8 or 16; 0 = library choice, a
+ *     per-ring table measured on MI355X: 4 for the 8-slice field; 8 for
+ *     the 4-slice field up to four outputs per pass; 16, 8 or 4 for the
+ *     6- and 10-slice fields at one, up to four, or more outputs). */
 int pyrit_encode_ex(const pyrit_plan *plan, const uint8_t *const *data, uint8_t *const *parity,
                     size_t slice_bytes, size_t slice_pitch, int vec_bytes, void *stream);
 
