@@ -101,18 +101,35 @@ class Arena:
         return self.buf[off:off + nbytes]
 
 
-def stripe_buffers(st, arena):
-    import paper_1709_00178_amd as P
+def stripe_buffers(st, arena, fill=True):
+    """Device blocks of one stripe (inputs filled with the generator unless
+    fill is False; see fill_inputs)."""
     from paper_1709_00178_amd import workloads as W
     ins = list(W.survivors(st))
     outs = list(st.erased) if st.erased else list(range(st.k, st.k + st.m))
     blocks = [None] * (st.k + st.m)
     for b in ins:
         blocks[b] = arena.take(st.block_len)
-        P.fill_random(blocks[b], st.key(b), nrandom=st.nrandom)
     for b in outs:
         blocks[b] = arena.take(st.block_len)
+    if fill:
+        fill_inputs([st], [blocks])
     return blocks
+
+
+def fill_inputs(stripes, block_lists, nrandom=None):
+    """Fill the input blocks of many stripes with the generator in one kernel
+    launch; nrandom(st) gives a stripe's random bytes per block (default
+    st.nrandom)."""
+    import paper_1709_00178_amd as P
+    from paper_1709_00178_amd import workloads as W
+    dst, keys, nrand = [], [], []
+    for st, blocks in zip(stripes, block_lists):
+        for b in W.survivors(st):
+            dst.append(blocks[b])
+            keys.append(st.key(b))
+            nrand.append(nrandom(st) if nrandom else st.nrandom)
+    P.fill_random_blocks(dst, keys, nrand)
 
 
 def arena_bytes(stripes, skew=0):
@@ -270,7 +287,7 @@ def bench_c1(args, stream, out, log):
     packed = W.c1()
     padded = dataclasses.replace(packed, pad=4096)
     st = padded
-    res_packed, *_ = c1_layout(args, stream, packed, 0, batched=False)
+    res_packed, *_ = c1_layout(args, stream, packed, 0, batched=True)
     torch.cuda.empty_cache()
     res, plan, blocks, batch, arena = c1_layout(args, stream, padded, BLOCK_SKEW, batched=True)
 
@@ -388,7 +405,8 @@ def bench_c1_stripes(args, stream, out, log):
                         seed=base.seed, pad=4096) for i in range(64)]
     plan = P.Plan(base.w, base.n, base.p, base.k, base.m)
     arena = Arena(arena_bytes(stripes, BLOCK_SKEW), BLOCK_SKEW)
-    bl = [stripe_buffers(st, arena) for st in stripes]
+    bl = [stripe_buffers(st, arena, fill=False) for st in stripes]
+    fill_inputs(stripes, bl)
     batch, cfg, _ = autotune.tuned_batch([(plan, [], b, st.S, st.pitch) for st, b in zip(stripes, bl)],
                                          stream, log=log)
 
@@ -477,7 +495,8 @@ def bench_paper_shapes(args, stream, out, log):
             arena = Arena(arena_bytes([st], BLOCK_SKEW), BLOCK_SKEW)
             bl = stripe_buffers(st, arena)
             passes = -(-m // PLAIN_OUTPUTS_PER_PASS_N9)
-            moved = (passes * k + m) * w * st.S
+            moved = (k + m) * w * st.S  # algorithmic: every block read or written once
+            reread = (passes * k + m) * w * st.S  # with each pass re-reading the data
             into = row if B == 1 << 20 else row.setdefault("blocks_16MiB", {"block_bytes": B})
             if B == 1 << 20:
                 row["block_bytes"] = B
@@ -490,6 +509,8 @@ def bench_paper_shapes(args, stream, out, log):
                 if B != 1 << 20:
                     r["GBps_moved"] = round(moved / (ms * 1e-3) / 1e9, 1)
                     r["frac_of_peak"] = round(moved / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
+                    r["passes"] = passes
+                    r["GBps_with_pass_rereads"] = round(reread / (ms * 1e-3) / 1e9, 1)
                 into[tr] = r
             del arena, bl
             torch.cuda.empty_cache()
@@ -508,7 +529,8 @@ def bench_c2(args, stream, out, log):
     st0 = stripes[0]
     plan = P.Plan(st0.w, st0.n, st0.p, st0.k, st0.m)
     arena = Arena(arena_bytes(stripes, BLOCK_SKEW), BLOCK_SKEW)
-    bl = [stripe_buffers(st, arena) for st in stripes]
+    bl = [stripe_buffers(st, arena, fill=False) for st in stripes]
+    fill_inputs(stripes, bl)
     batch, cfg, _ = autotune.tuned_batch([(plan, [], b, st.S) for st, b in zip(stripes, bl)],
                                          stream, log=log)
     torch.cuda.synchronize()
@@ -583,17 +605,10 @@ def bench_c3(args, stream, out, log):
         else:
             stripes = base
         arena = Arena(arena_bytes(stripes, BLOCK_SKEW), BLOCK_SKEW)
-        bl = []
-        for st in stripes:
-            ins = list(W.survivors(st))
-            outs = list(st.erased) if st.erased else list(range(st.k, st.k + st.m))
-            blocks = [None] * (st.k + st.m)
-            for b in ins + outs:
-                blocks[b] = arena.take(st.block_len)
-            for b in ins:
-                # padded blocks: generator bytes over the whole block memory
-                P.fill_random(blocks[b], st.key(b), nrandom=st.B if not st.pad else st.block_len)
-            bl.append(blocks)
+        bl = [stripe_buffers(st, arena, fill=False) for st in stripes]
+        # all inputs in one launch; padded blocks carry generator bytes over
+        # their whole memory
+        fill_inputs(stripes, bl, nrandom=lambda st: st.B if not st.pad else st.block_len)
         items = [(plans[(st.w, st.n, st.p, st.k, st.m)], list(st.erased), b, st.S, st.pitch)
                  for st, b in zip(stripes, bl)]
         batch, cfg, _ = autotune.tuned_batch(items, stream, log=log)

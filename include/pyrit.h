@@ -27,7 +27,9 @@
  * of x^i (p includes its x^w term: x^8+x^5+x^4+x^3+1 is 0x139).
  *
  * Conventions.  Every entry point returns PYRIT_OK (0) or a negative
- * PYRIT_E* code; no C++ exception crosses this boundary.  Pointer arrays
+ * PYRIT_E* code; no C++ exception crosses this boundary (a failed host
+ * allocation inside the library returns PYRIT_ENOMEM, leaving every object
+ * as it was before the call).  Pointer arrays
  * (data[], parity[], blocks[]) are host arrays of device pointers; the
  * library copies them before returning.  Device work is enqueued on the
  * caller's stream (a hipStream_t passed as void*, NULL = the null stream)
@@ -59,7 +61,8 @@ enum {
   PYRIT_EUNSUPPORTED = -9, /* no device kernel for this (w, n, p) ring */
   PYRIT_EHIP = -10,        /* a HIP runtime call failed */
   PYRIT_ENOMEM = -11,      /* host or device allocation failed */
-  PYRIT_EBUSY = -12        /* resource cap reached (serving admission) */
+  PYRIT_EBUSY = -12,       /* resource cap reached (serving admission) */
+  PYRIT_EINTERNAL = -13    /* an unexpected internal failure (a bug) */
 };
 
 #define PYRIT_KMAX 64      /* maximum data blocks per stripe */
@@ -137,11 +140,22 @@ typedef struct pyrit_plan pyrit_plan;
 enum { PYRIT_TRANSFORM_EMBEDDING = 0, PYRIT_TRANSFORM_PARITY = 1 };
 
 /* Build the lifted XOR schedule of the systematic code [I_k; G] (G is the
- * m x k row-major parity part, host memory, copied).  Validates the ring
- * (pyrit_ring_check), 1 <= k <= PYRIT_KMAX, 1 <= m <= PYRIT_MMAX,
- * k + m <= 2^w and every G entry < 2^w.  A plan for a ring without a device
- * kernel is still created (host queries work); device calls on it return
- * PYRIT_EUNSUPPORTED.  *out receives the plan. */
+ * m x k row-major parity part, host memory, copied).
+ *   Follows Sec. II-A (the field F_2[x]/(p) inside R_{2,n} = F_2[x]/(x^n+1)
+ *   when p divides x^n + 1, n odd) and Sec. II-B (the sparse transform: each
+ *   coefficient G[i][j] is replaced by a ring element of least Hamming
+ *   weight congruent to it mod p, so the product by it costs one rotated
+ *   copy of the block per nonzero coefficient); the code is the systematic
+ *   MDS code of Sec. III, whose parity part is G.
+ *   Validates the ring (pyrit_ring_check), 1 <= k <= PYRIT_KMAX,
+ *   1 <= m <= PYRIT_MMAX, k + m <= 2^w and every G entry < 2^w.  A plan for
+ *   a ring without a device kernel is still created (host queries work);
+ *   device calls on it return PYRIT_EUNSUPPORTED.
+ *   Ownership: *out receives a plan the caller releases with
+ *   pyrit_plan_destroy; G is not referenced after the call.
+ *   Errors: PYRIT_EINVAL (NULL G or out, k or m out of range),
+ *   PYRIT_ENOTIRRED, PYRIT_ENOTDIV, PYRIT_ETOOLONG, PYRIT_ERANGE,
+ *   PYRIT_ENOMEM; *out is NULL after any error. */
 int pyrit_plan_create(int w, int n, uint32_t p, int k, int m, const uint16_t *G,
                       pyrit_plan **out);
 
@@ -178,18 +192,39 @@ int pyrit_decode_matrix(const pyrit_plan *plan, const int *erased, int n_erased,
 
 /* ------------------------------------------------------------- device calls */
 
-/* Encode: parity[i] = sum_j G[i][j] * data[j] for i < m, computed as
- * rotated-slice XORs in R_{2,n} and reduced mod p (for a PARITY plan, the
- * parity-transform code of PYRIT_TRANSFORM_PARITY).  data: k device pointers,
- * parity: m device pointers (host arrays), each block w * slice_bytes bytes.
- * Outputs must not alias inputs. */
+/* Encode: parity[i] = sum_j G[i][j] * data[j] for i < m, symbol by symbol.
+ *   Follows Sec. II-B (each G[i][j] is its sparse ring representative c_ij,
+ *   and multiplying by x^s in R_{2,n} rotates the n ring slices by s), the
+ *   embedding transform of Sec. II-C.2 / II-D.2 (a block enters the ring as
+ *   its w slices followed by n - w zero slices, which are never stored or
+ *   loaded) and Prop. 2 (reduction mod p maps the ring sum back to the field
+ *   product, so each parity's n ring slices are reduced once, after its last
+ *   input).  A PARITY plan computes the parity-transform code instead
+ *   (Sec. II-C.1 / II-D.1, PYRIT_TRANSFORM_PARITY).
+ *   data: k device pointers, parity: m device pointers (host arrays, copied
+ *   before the call returns); each block is w slices of slice_bytes bytes,
+ *   packed.  Outputs must not alias inputs.  Enqueued on `stream`; the
+ *   caller keeps the buffers alive until it completes.
+ *   Errors: PYRIT_EINVAL (NULL plan, array or entry), PYRIT_EALIGN (slice
+ *   size not a positive multiple of 64, pointer not 16-byte aligned),
+ *   PYRIT_EUNSUPPORTED (no kernel for the ring), PYRIT_EHIP (launch). */
 int pyrit_encode(const pyrit_plan *plan, const uint8_t *const *data, uint8_t *const *parity,
                  size_t slice_bytes, void *stream);
 
 /* Decode: blocks holds k + m device pointers (data then parity).  Entries
  * listed in erased[] (distinct ids, n_erased <= m) are outputs; the first k
- * non-erased entries are read.  The decoding matrix is built on the host
- * (cached per pattern) and the encode kernel runs with it. */
+ * non-erased entries are read.
+ *   Follows Sec. IV-C: the decoding matrix depends on the loss pattern.  It
+ *   is built on the host (pyrit_decode_matrix: the survivors' rows A of
+ *   [I; G] inverted over GF(2^w), D = G_E * A^-1, cached per pattern on the
+ *   plan), lifted by the sparse transform of Sec. II-B, and the encode
+ *   kernels run with D in place of G, the survivors as inputs and the
+ *   erased blocks as outputs.
+ *   Layout, ownership and asynchrony as pyrit_encode; entries that are
+ *   neither read nor written may be NULL.
+ *   Errors: those of pyrit_encode, PYRIT_EINVAL (erased id out of range or
+ *   repeated), PYRIT_ETOOMANY (n_erased > m), PYRIT_ESINGULAR (a user G
+ *   whose surviving rows are not invertible), PYRIT_ENOMEM. */
 int pyrit_decode(const pyrit_plan *plan, const int *erased, int n_erased,
                  uint8_t *const *blocks, size_t slice_bytes, void *stream);
 
@@ -238,8 +273,19 @@ int pyrit_from_sliced(int w, const uint8_t *sliced, size_t slice_pitch, size_t n
  * bytes < nrandom, zero beyond.  nbytes must be a multiple of 8. */
 int pyrit_fill_random(uint8_t *dst, size_t nbytes, size_t nrandom, uint64_t key, void *stream);
 
-/* Device-to-device copy with the library's streaming copy kernel (16 bytes
- * per lane); nbytes a multiple of 16.  A bandwidth reference. */
+/* pyrit_fill_random for n buffers in one kernel launch: buffer i is
+ * dst[i] (device, 8-byte aligned), nbytes[i] bytes (a multiple of 8), filled
+ * with the stream of key keys[i], random for bytes < nrandom[i] (nrandom
+ * NULL: all bytes) and zero beyond.  The host arrays are copied to a device
+ * table that the call allocates and frees; the call returns once the fill
+ * has completed on `stream`.  Buffers must not overlap.  Errors:
+ * PYRIT_EINVAL, PYRIT_ENOMEM, PYRIT_EHIP. */
+int pyrit_fill_random_blocks(uint8_t *const *dst, const size_t *nbytes, const size_t *nrandom,
+                             const uint64_t *keys, int n, void *stream);
+
+/* Device-to-device copy with the library's streaming copy kernel (16-byte
+ * non-temporal loads, stores with the coding kernels' SC1 policy, as two
+ * 8-byte stores); nbytes a multiple of 16.  A bandwidth reference. */
 int pyrit_copy(uint8_t *dst, const uint8_t *src, size_t nbytes, void *stream);
 
 /* ------------------------------------------------------------------ batches

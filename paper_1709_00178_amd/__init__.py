@@ -15,7 +15,7 @@ import numpy as np
 from ._lib import lib
 
 __all__ = ["PyritError", "Plan", "Batch", "ring_check", "ring_supported", "lift", "ring_reduce",
-           "ring_mul", "gf_mul", "cauchy", "fill_random", "copy", "version"]
+           "ring_mul", "gf_mul", "cauchy", "fill_random", "fill_random_blocks", "copy", "version"]
 
 PYRIT_OK = 0
 
@@ -338,6 +338,23 @@ def fill_random(buf, key: int, nrandom: int | None = None, nbytes: int | None = 
         nrandom = nbytes
     _check(lib().pyrit_fill_random(_dev_ptr(buf, nbytes), nbytes, nrandom, key & ((1 << 64) - 1),
                                    _stream_handle(stream)))
+
+
+def fill_random_blocks(bufs, keys, nrandom=None, stream=None) -> None:
+    """Fill many device buffers with their seeded SplitMix64 streams in one
+    kernel launch (pyrit_fill_random_blocks): buffer i gets key keys[i],
+    random bytes up to nrandom[i] (None: the whole buffer), zeros beyond.
+    Returns once the fill has completed."""
+    bufs = list(bufs)
+    n = len(bufs)
+    if len(keys) != n or (nrandom is not None and len(nrandom) != n):
+        raise ValueError("need one key (and one nrandom) per buffer")
+    sizes = [b.numel() * b.element_size() for b in bufs]
+    dst = (ctypes.c_void_p * max(1, n))(*[_dev_ptr(b, s) for b, s in zip(bufs, sizes)])
+    nb = (ctypes.c_size_t * max(1, n))(*sizes)
+    ks = (ctypes.c_uint64 * max(1, n))(*[k & ((1 << 64) - 1) for k in keys])
+    nr = None if nrandom is None else (ctypes.c_size_t * max(1, n))(*nrandom)
+    _check(lib().pyrit_fill_random_blocks(dst, nb, nr, ks, n, _stream_handle(stream)))
 
 
 def copy(dst, src, nbytes: int | None = None, stream=None) -> None:

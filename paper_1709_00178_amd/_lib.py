@@ -43,6 +43,7 @@ SIGNATURES = {
     "pyrit_decode_ex": (c_int, [c_vp, c_vp, c_int, c_vp, c_size, c_size, c_vp]),
     "pyrit_decode": (c_int, [c_vp, c_vp, c_int, c_vp, c_size, c_vp]),
     "pyrit_fill_random": (c_int, [c_vp, c_size, c_size, c_u64, c_vp]),
+    "pyrit_fill_random_blocks": (c_int, [c_vp, c_vp, c_vp, c_vp, c_int, c_vp]),
     "pyrit_copy": (c_int, [c_vp, c_vp, c_size, c_vp]),
     "pyrit_to_sliced": (c_int, [c_int, c_vp, c_size, c_vp, c_size, c_vp]),
     "pyrit_from_sliced": (c_int, [c_int, c_vp, c_size, c_size, c_vp, c_vp]),

@@ -97,7 +97,7 @@ __device__ __forceinline__ void run_chunk(const PassDesc &pd, uint32_t base, uin
   constexpr int V = kBatchV[RING];
   typedef typename dev::Vec<V>::T T;
   const TableSrc src = table_src(pd);
-  const uint32_t col = base + lane * 4u * V;
+  const uint32_t col = lane_col(base, lane, V);
   dev::code_column<R.w, R.n, R.p, batch_max_out(RING), V, KS, R.parity>(src, col, col < src.S(), part,
                                                                           (T *)xch);
 }
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(WG) void batch_grid_kernel(const BatchArgs a) {
   const uint32_t first = starts[lo];
   const uint32_t ring = pd.ring;
   const uint32_t chunk = chunk_bytes(ring);
-  const uint32_t base = ((b - first) * (WG / 64 / KS) + wave / KS) * chunk;
+  const uint32_t base = grid_chunk_base(b - first, wave, kPairs, KS, chunk);
   const uint32_t part = wave % KS;
   // A workgroup's first chunk never starts past the end of its pass; a later
   // one may.  Such a chunk has nothing to code.  A split-K pair still meets

@@ -317,50 +317,52 @@ extern "C" {
 
 int pyrit_batch_create(const pyrit_batch_item *items, int n_items, const pyrit_tune *tune,
                        pyrit_batch **out) {
-  if (!out || n_items < 0 || (n_items > 0 && !items)) return PYRIT_EINVAL;
-  *out = nullptr;
-  pyrit_tune t{};
-  if (tune) t = *tune;
-  int rc = batch_check_tune(&t);
-  if (rc) return rc;
-  std::unique_ptr<pyrit_batch> b(new (std::nothrow) pyrit_batch());
-  if (!b) return PYRIT_ENOMEM;
-  // Validate the items before touching the device; the image embeds device
-  // addresses, so it is built again once the allocation exists.
-  BatchImage probe;
-  rc = build_batch_image(items, n_items, t, 1, 0, &probe);
-  if (rc) return rc;
-  int grid = 0;
-  if (t.mode != kModeGrid) {
-    rc = batch_resident_grid(t, &grid);
+  return abi_guard([&]() -> int {
+    if (!out || n_items < 0 || (n_items > 0 && !items)) return PYRIT_EINVAL;
+    *out = nullptr;
+    pyrit_tune t{};
+    if (tune) t = *tune;
+    int rc = batch_check_tune(&t);
     if (rc) return rc;
-    rc = build_batch_image(items, n_items, t, grid, 0, &probe);
+    std::unique_ptr<pyrit_batch> b(new (std::nothrow) pyrit_batch());
+    if (!b) return PYRIT_ENOMEM;
+    // Validate the items before touching the device; the image embeds device
+    // addresses, so it is built again once the allocation exists.
+    BatchImage probe;
+    rc = build_batch_image(items, n_items, t, 1, 0, &probe);
     if (rc) return rc;
-  }
-  if (hipMalloc(&b->dmem, probe.img.size()) != hipSuccess) return PYRIT_ENOMEM;
-  rc = build_batch_image(items, n_items, t, grid, (uint64_t)(uintptr_t)b->dmem, &b->bi);
-  if (rc) return rc;
-  if (hipMemcpy(b->dmem, b->bi.img.data(), b->bi.img.size(), hipMemcpyHostToDevice) != hipSuccess)
-    return PYRIT_EHIP;
-  b->args = image_args(b->bi, b->dmem);
-  if (b->bi.n_items == 0) {
+    int grid = 0;
+    if (t.mode != kModeGrid) {
+      rc = batch_resident_grid(t, &grid);
+      if (rc) return rc;
+      rc = build_batch_image(items, n_items, t, grid, 0, &probe);
+      if (rc) return rc;
+    }
+    if (hipMalloc(&b->dmem, probe.img.size()) != hipSuccess) return PYRIT_ENOMEM;
+    rc = build_batch_image(items, n_items, t, grid, (uint64_t)(uintptr_t)b->dmem, &b->bi);
+    if (rc) return rc;
+    if (hipMemcpy(b->dmem, b->bi.img.data(), b->bi.img.size(), hipMemcpyHostToDevice) != hipSuccess)
+      return PYRIT_EHIP;
+    b->args = image_args(b->bi, b->dmem);
+    if (b->bi.n_items == 0) {
+      *out = b.release();
+      return PYRIT_OK;
+    }
+    if (hipGraphCreate(&b->graph, 0) != hipSuccess) return PYRIT_EHIP;
+    hipKernelNodeParams kp{};
+    void *kargs[] = {&b->args};
+    kp.func = const_cast<void *>(kernel_fn(b->bi.mode, b->bi.wg, b->bi.xcd_order, b->bi.split));
+    kp.gridDim = dim3(b->bi.grid);
+    kp.blockDim = dim3(b->bi.wg);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = kargs;
+    kp.extra = nullptr;
+    hipGraphNode_t node;
+    if (hipGraphAddKernelNode(&node, b->graph, nullptr, 0, &kp) != hipSuccess) return PYRIT_EHIP;
+    if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) return PYRIT_EHIP;
     *out = b.release();
     return PYRIT_OK;
-  }
-  if (hipGraphCreate(&b->graph, 0) != hipSuccess) return PYRIT_EHIP;
-  hipKernelNodeParams kp{};
-  void *kargs[] = {&b->args};
-  kp.func = const_cast<void *>(kernel_fn(b->bi.mode, b->bi.wg, b->bi.xcd_order, b->bi.split));
-  kp.gridDim = dim3(b->bi.grid);
-  kp.blockDim = dim3(b->bi.wg);
-  kp.sharedMemBytes = 0;
-  kp.kernelParams = kargs;
-  kp.extra = nullptr;
-  hipGraphNode_t node;
-  if (hipGraphAddKernelNode(&node, b->graph, nullptr, 0, &kp) != hipSuccess) return PYRIT_EHIP;
-  if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) return PYRIT_EHIP;
-  *out = b.release();
-  return PYRIT_OK;
+  });
 }
 
 int pyrit_batch_launch(pyrit_batch *batch, void *stream) {
@@ -390,25 +392,27 @@ void pyrit_batch_destroy(pyrit_batch *batch) { delete batch; }
 int pyrit_batch_describe(const pyrit_batch_item *items, int n_items, const pyrit_tune *tune,
                          int *n_passes, int *n_work_items, uint64_t *moved_bytes, int *grid,
                          uint64_t *xcd_bytes) {
-  if (n_items < 0 || (n_items > 0 && !items)) return PYRIT_EINVAL;
-  pyrit_tune t{};
-  if (tune) t = *tune;
-  int rc = batch_check_tune(&t);
-  if (rc) return rc;
-  // the resident grid of the persistent modes is a device query: take it
-  // from the caller instead
-  if (t.mode != kModeGrid && t.grid <= 0) return PYRIT_EINVAL;
-  const int resident = t.mode == kModeQueue ? std::max(t.grid, kGroups) : t.grid;
-  BatchImage bi;
-  rc = build_batch_image(items, n_items, t, t.mode == kModeGrid ? 0 : resident, 0, &bi);
-  if (rc) return rc;
-  if (n_passes) *n_passes = (int)bi.n_passes;
-  if (n_work_items) *n_work_items = (int)bi.n_items;
-  if (moved_bytes) *moved_bytes = bi.moved;
-  if (grid) *grid = bi.grid;
-  if (xcd_bytes)
-    for (uint32_t x = 0; x < kXcds; ++x) xcd_bytes[x] = bi.xcd_bytes[x];
-  return PYRIT_OK;
+  return abi_guard([&]() -> int {
+    if (n_items < 0 || (n_items > 0 && !items)) return PYRIT_EINVAL;
+    pyrit_tune t{};
+    if (tune) t = *tune;
+    int rc = batch_check_tune(&t);
+    if (rc) return rc;
+    // the resident grid of the persistent modes is a device query: take it
+    // from the caller instead
+    if (t.mode != kModeGrid && t.grid <= 0) return PYRIT_EINVAL;
+    const int resident = t.mode == kModeQueue ? std::max(t.grid, kGroups) : t.grid;
+    BatchImage bi;
+    rc = build_batch_image(items, n_items, t, t.mode == kModeGrid ? 0 : resident, 0, &bi);
+    if (rc) return rc;
+    if (n_passes) *n_passes = (int)bi.n_passes;
+    if (n_work_items) *n_work_items = (int)bi.n_items;
+    if (moved_bytes) *moved_bytes = bi.moved;
+    if (grid) *grid = bi.grid;
+    if (xcd_bytes)
+      for (uint32_t x = 0; x < kXcds; ++x) xcd_bytes[x] = bi.xcd_bytes[x];
+    return PYRIT_OK;
+  });
 }
 
 }  // extern "C"

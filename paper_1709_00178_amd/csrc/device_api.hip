@@ -1,9 +1,12 @@
 // C ABI device entry points: encode, decode, fill, copy.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
+#include <vector>
 
 #include "internal.hpp"
+#include "ring_kernels.hpp"
 
 namespace pyrit {
 
@@ -86,13 +89,15 @@ extern "C" {
 
 int pyrit_encode_ex(const pyrit_plan *plan, const uint8_t *const *data, uint8_t *const *parity,
                     size_t slice_bytes, size_t slice_pitch, int vec_bytes, void *stream) {
-  if (!plan || !data || !parity) return PYRIT_EINVAL;
-  if (plan->ring < 0) return PYRIT_EUNSUPPORTED;
-  if (vec_bytes != 0 && vec_bytes != 4 && vec_bytes != 8 && vec_bytes != 16) return PYRIT_EINVAL;
-  int rc = check_slices(plan->w, slice_bytes, &slice_pitch);
-  if (rc) return rc;
-  return run_passes(plan, data, parity, plan->m, plan->L.data(), slice_bytes, slice_pitch,
-                    vec_bytes, stream);
+  return abi_guard([&]() -> int {
+    if (!plan || !data || !parity) return PYRIT_EINVAL;
+    if (plan->ring < 0) return PYRIT_EUNSUPPORTED;
+    if (vec_bytes != 0 && vec_bytes != 4 && vec_bytes != 8 && vec_bytes != 16) return PYRIT_EINVAL;
+    int rc = check_slices(plan->w, slice_bytes, &slice_pitch);
+    if (rc) return rc;
+    return run_passes(plan, data, parity, plan->m, plan->L.data(), slice_bytes, slice_pitch,
+                      vec_bytes, stream);
+  });
 }
 
 int pyrit_encode(const pyrit_plan *plan, const uint8_t *const *data, uint8_t *const *parity,
@@ -102,20 +107,22 @@ int pyrit_encode(const pyrit_plan *plan, const uint8_t *const *data, uint8_t *co
 
 int pyrit_decode_ex(const pyrit_plan *plan, const int *erased, int n_erased, uint8_t *const *blocks,
                     size_t slice_bytes, size_t slice_pitch, void *stream) {
-  if (!plan || !blocks) return PYRIT_EINVAL;
-  if (plan->ring < 0) return PYRIT_EUNSUPPORTED;
-  int rc = check_slices(plan->w, slice_bytes, &slice_pitch);
-  if (rc) return rc;
-  std::shared_ptr<const DecodeEntry> ent;
-  rc = decode_entry(plan, erased, n_erased, &ent);
-  if (rc) return rc;
-  if (ent->outs.empty()) return PYRIT_OK;
-  const uint8_t *in[PYRIT_KMAX];
-  uint8_t *out[PYRIT_MMAX];
-  for (int j = 0; j < plan->k; ++j) in[j] = blocks[ent->surv[j]];
-  for (size_t e = 0; e < ent->outs.size(); ++e) out[e] = blocks[ent->outs[e]];
-  return run_passes(plan, in, out, (int)ent->outs.size(), ent->L.data(), slice_bytes, slice_pitch,
-                    0, stream);
+  return abi_guard([&]() -> int {
+    if (!plan || !blocks) return PYRIT_EINVAL;
+    if (plan->ring < 0) return PYRIT_EUNSUPPORTED;
+    int rc = check_slices(plan->w, slice_bytes, &slice_pitch);
+    if (rc) return rc;
+    std::shared_ptr<const DecodeEntry> ent;
+    rc = decode_entry(plan, erased, n_erased, &ent);
+    if (rc) return rc;
+    if (ent->outs.empty()) return PYRIT_OK;
+    const uint8_t *in[PYRIT_KMAX];
+    uint8_t *out[PYRIT_MMAX];
+    for (int j = 0; j < plan->k; ++j) in[j] = blocks[ent->surv[j]];
+    for (size_t e = 0; e < ent->outs.size(); ++e) out[e] = blocks[ent->outs[e]];
+    return run_passes(plan, in, out, (int)ent->outs.size(), ent->L.data(), slice_bytes, slice_pitch,
+                      0, stream);
+  });
 }
 
 int pyrit_decode(const pyrit_plan *plan, const int *erased, int n_erased, uint8_t *const *blocks,
@@ -134,28 +141,70 @@ __device__ __forceinline__ uint64_t splitmix_mix(uint64_t z) {
   return z ^ (z >> 31);
 }
 
-// Word q of the buffer: mix(key + (q + 1) * golden gamma); bytes past
+// Word q of a buffer: mix(key + (q + 1) * golden gamma); bytes past
 // nrandom are zero.
+__device__ __forceinline__ uint64_t fill_word(uint64_t key, uint64_t q, uint64_t nrandom) {
+  uint64_t v = splitmix_mix(key + (q + 1) * 0x9E3779B97F4A7C15ull);
+  const uint64_t b0 = q * 8;
+  if (b0 + 8 > nrandom) {
+    const uint64_t keep = nrandom > b0 ? nrandom - b0 : 0;  // 0..7 bytes kept
+    v = keep ? (v & ((1ull << (8 * keep)) - 1)) : 0;
+  }
+  return v;
+}
+
 __global__ __launch_bounds__(256) void fill_random_kernel(uint64_t *dst, uint64_t nwords,
                                                           uint64_t nrandom, uint64_t key) {
   const uint64_t stride = (uint64_t)gridDim.x * 256u;
-  for (uint64_t q = (uint64_t)blockIdx.x * 256u + threadIdx.x; q < nwords; q += stride) {
-    uint64_t v = splitmix_mix(key + (q + 1) * 0x9E3779B97F4A7C15ull);
-    const uint64_t b0 = q * 8;
-    if (b0 + 8 > nrandom) {
-      const uint64_t keep = nrandom > b0 ? nrandom - b0 : 0;  // 0..7 bytes kept
-      v = keep ? (v & ((1ull << (8 * keep)) - 1)) : 0;
+  for (uint64_t q = (uint64_t)blockIdx.x * 256u + threadIdx.x; q < nwords; q += stride)
+    dst[q] = fill_word(key, q, nrandom);
+}
+
+// Many buffers in one launch.  Buffer i is cut into tiles of kFillTile
+// words; tiles are numbered buffer by buffer (first_tile[i] is buffer i's
+// first), and a workgroup finds its buffer by a binary search over them.
+constexpr uint64_t kFillTile = 256u * 16u;
+
+struct FillRec {
+  uint64_t dst, nwords, nrandom, key, first_tile;
+};
+
+__global__ __launch_bounds__(256) void fill_blocks_kernel(const FillRec *recs, uint32_t n,
+                                                          uint64_t n_tiles) {
+  for (uint64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (recs[mid].first_tile <= t) lo = mid;
+      else hi = mid;
     }
-    dst[q] = v;
+    const FillRec r = recs[lo];
+    uint64_t *dst = (uint64_t *)r.dst;
+    const uint64_t q0 = (t - r.first_tile) * kFillTile;
+    const uint64_t q1 = q0 + kFillTile < r.nwords ? q0 + kFillTile : r.nwords;
+    for (uint64_t q = q0 + threadIdx.x; q < q1; q += 256u) dst[q] = fill_word(r.key, q, r.nrandom);
   }
 }
 
-typedef uint32_t cu32x4 __attribute__((ext_vector_type(4)));
-
-__global__ __launch_bounds__(256) void copy_kernel(cu32x4 *dst, const cu32x4 *src, uint64_t n16) {
+// Device copy with the coding kernels' memory policies: non-temporal 16-byte
+// loads and SC1 stores (the store policy that measured fastest on MI355X).
+// Each wave moves 1 KiB per step through buffer descriptors based at the
+// wave's first 16-byte unit; every 16-byte unit is stored as two 8-byte
+// stores (a wider store reads its data registers after it issues, which
+// generated code has been seen to overwrite before the read).
+__global__ __launch_bounds__(256) void copy_kernel(uint8_t *dst, const uint8_t *src, uint64_t n16) {
+  const uint32_t lane = threadIdx.x & 63u;
   const uint64_t stride = (uint64_t)gridDim.x * 256u;
-  for (uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x; i < n16; i += stride)
-    __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+  for (uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x; i < n16; i += stride) {
+    const uint64_t u0 = i - lane;  // the wave's first unit (the same in every lane)
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u0);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u0 >> 32));
+    const uint64_t off = (((uint64_t)hi << 32) | lo) * 16u;
+    const __amdgpu_buffer_rsrc_t rs = dev::block_rsrc(src + off, 1024u);
+    const __amdgpu_buffer_rsrc_t rd = dev::block_rsrc(dst + off, 1024u);
+    const dev::u32x4 x = dev::bload<4>(rs, lane * 16u, 0u);
+    dev::bstore<4>(x, rd, lane * 16u, 0u);
+  }
 }
 
 static unsigned grid_for(uint64_t items) {
@@ -179,13 +228,50 @@ int pyrit_fill_random(uint8_t *dst, size_t nbytes, size_t nrandom, uint64_t key,
   return hipGetLastError() == hipSuccess ? PYRIT_OK : PYRIT_EHIP;
 }
 
+int pyrit_fill_random_blocks(uint8_t *const *dst, const size_t *nbytes, const size_t *nrandom,
+                             const uint64_t *keys, int n, void *stream) {
+  return abi_guard([&]() -> int {
+    if (n < 0 || (n > 0 && (!dst || !nbytes || !keys))) return PYRIT_EINVAL;
+    std::vector<FillRec> recs;
+    recs.reserve((size_t)n);
+    uint64_t tiles = 0;
+    for (int i = 0; i < n; ++i) {
+      if (!dst[i] || nbytes[i] % 8 != 0 || ((uintptr_t)dst[i] & 7u)) return PYRIT_EINVAL;
+      if (nbytes[i] == 0) continue;
+      const uint64_t nr = nrandom ? std::min<uint64_t>(nrandom[i], nbytes[i]) : nbytes[i];
+      const uint64_t nw = nbytes[i] / 8;
+      recs.push_back({(uint64_t)(uintptr_t)dst[i], nw, nr, keys[i], tiles});
+      tiles += (nw + kFillTile - 1) / kFillTile;
+    }
+    if (recs.empty()) return PYRIT_OK;
+    if (recs.size() > 0xFFFFFFFFull) return PYRIT_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t bytes = recs.size() * sizeof(FillRec);
+    void *table = nullptr;
+    if (hipMalloc(&table, bytes) != hipSuccess) return PYRIT_ENOMEM;
+    int rc = PYRIT_OK;
+    if (hipMemcpyAsync(table, recs.data(), bytes, hipMemcpyHostToDevice, st) != hipSuccess) {
+      rc = PYRIT_EHIP;
+    } else {
+      const uint64_t grid = std::min<uint64_t>(tiles, 256ull * 32);
+      hipLaunchKernelGGL(fill_blocks_kernel, dim3((unsigned)grid), dim3(256), 0, st,
+                         (const FillRec *)table, (uint32_t)recs.size(), tiles);
+      if (hipGetLastError() != hipSuccess) rc = PYRIT_EHIP;
+    }
+    // the table (and the host records the copy reads) must outlive the work
+    if (hipStreamSynchronize(st) != hipSuccess && rc == PYRIT_OK) rc = PYRIT_EHIP;
+    (void)hipFree(table);
+    return rc;
+  });
+}
+
 int pyrit_copy(uint8_t *dst, const uint8_t *src, size_t nbytes, void *stream) {
   if (!dst || !src || nbytes % 16 != 0 || ((uintptr_t)dst & 15u) || ((uintptr_t)src & 15u))
     return PYRIT_EINVAL;
   if (nbytes == 0) return PYRIT_OK;
   const uint64_t n16 = nbytes / 16;
-  hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n16)), dim3(256), 0, (hipStream_t)stream,
-                     (cu32x4 *)dst, (const cu32x4 *)src, (uint64_t)n16);
+  hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n16)), dim3(256), 0, (hipStream_t)stream, dst,
+                     src, (uint64_t)n16);
   return hipGetLastError() == hipSuccess ? PYRIT_OK : PYRIT_EHIP;
 }
 

@@ -4,6 +4,8 @@
 #include <cstdint>
 #include <memory>
 #include <mutex>
+#include <new>
+#include <stdexcept>
 #include <unordered_map>
 #include <vector>
 
@@ -31,6 +33,23 @@ struct DecodeEntry {
 
 // Lifted representative of every field element of a ring (size 2^w).
 const std::vector<uint32_t> &lift_table(int w, int n, uint32_t p);
+
+// Runs the body of a C entry point so that no C++ exception crosses the C
+// ABI: a failed host allocation becomes PYRIT_ENOMEM, anything else
+// PYRIT_EINTERNAL.  Bodies hold their resources in RAII objects, so an
+// exception leaves nothing behind.
+template <class F>
+int abi_guard(F &&body) noexcept {
+  try {
+    return body();
+  } catch (const std::bad_alloc &) {
+    return PYRIT_ENOMEM;
+  } catch (const std::length_error &) {
+    return PYRIT_ENOMEM;
+  } catch (...) {
+    return PYRIT_EINTERNAL;
+  }
+}
 
 }  // namespace pyrit
 

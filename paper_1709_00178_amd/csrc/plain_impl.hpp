@@ -16,7 +16,7 @@ __global__ __launch_bounds__(kPlainWG) void plain_pass_kernel(const PassArgs a) 
   __shared__ T xch[MO * R.w * 64];
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t part = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint32_t col = (blockIdx.x * 64u + lane) * (4u * V);
+  const uint32_t col = lane_col(plain_chunk_base(blockIdx.x, V), lane, V);
   dev::code_column<R.w, R.n, R.p, MO, V, 2, R.parity>(dev::KernargSrc{a}, col, col < a.S, part, xch);
 }
 

@@ -176,6 +176,7 @@ const char *pyrit_strerror(int code) {
     case PYRIT_EHIP: return "HIP runtime error";
     case PYRIT_ENOMEM: return "out of memory";
     case PYRIT_EBUSY: return "resource cap reached";
+    case PYRIT_EINTERNAL: return "internal error";
     default: return "unknown error";
   }
 }
@@ -194,12 +195,14 @@ int pyrit_ring_check(int w, int n, uint32_t p) {
 int pyrit_ring_supported(int w, int n, uint32_t p) { return ring_id(w, n, p) >= 0 ? 1 : 0; }
 
 int pyrit_lift(int w, int n, uint32_t p, uint32_t u, uint32_t *c) {
-  int rc = pyrit_ring_check(w, n, p);
-  if (rc) return rc;
-  if (!c) return PYRIT_EINVAL;
-  if (u >> w) return PYRIT_ERANGE;
-  *c = lift_table(w, n, p)[u];
-  return PYRIT_OK;
+  return abi_guard([&]() -> int {
+    int rc = pyrit_ring_check(w, n, p);
+    if (rc) return rc;
+    if (!c) return PYRIT_EINVAL;
+    if (u >> w) return PYRIT_ERANGE;
+    *c = lift_table(w, n, p)[u];
+    return PYRIT_OK;
+  });
 }
 
 int pyrit_ring_reduce(int w, int n, uint32_t p, uint32_t c, uint32_t *u) {
@@ -234,59 +237,61 @@ int pyrit_cauchy(int w, uint32_t p, int k, int m, uint16_t *G) {
 
 int pyrit_cauchy_light(int w, int n, uint32_t p, int k, int m, uint16_t *G, uint16_t *row_scale,
                        uint16_t *col_scale, int *weight) {
-  int rc = pyrit_ring_check(w, n, p);
-  if (rc) return rc;
-  rc = pyrit_cauchy(w, p, k, m, G);
-  if (rc) return rc;
-  const auto &lt = lift_table(w, n, p);
-  const uint32_t q = 1u << w;
-  std::vector<uint32_t> C((size_t)m * k), d(m, 1u), c(k, 1u);
-  for (size_t i = 0; i < C.size(); ++i) C[i] = G[i];
-  auto wt = [&](uint32_t u) { return __builtin_popcount(lt[u]); };
-  // Coordinate descent over the row and column multipliers: each step keeps
-  // the multiplier with the smallest total lifted weight of its row or
-  // column (ties: the smallest element), so the total never increases.
-  for (int round = 0; round < 16; ++round) {
-    bool changed = false;
-    for (int j = 0; j < k; ++j) {
-      uint32_t best = c[j];
-      long best_w = -1;
-      for (uint32_t a = 1; a < q; ++a) {
-        long s = 0;
-        for (int i = 0; i < m; ++i) s += wt(gf_mul(gf_mul(d[i], C[(size_t)i * k + j], p), a, p));
-        if (best_w < 0 || s < best_w) { best_w = s; best = a; }
+  return abi_guard([&]() -> int {
+    int rc = pyrit_ring_check(w, n, p);
+    if (rc) return rc;
+    rc = pyrit_cauchy(w, p, k, m, G);
+    if (rc) return rc;
+    const auto &lt = lift_table(w, n, p);
+    const uint32_t q = 1u << w;
+    std::vector<uint32_t> C((size_t)m * k), d(m, 1u), c(k, 1u);
+    for (size_t i = 0; i < C.size(); ++i) C[i] = G[i];
+    auto wt = [&](uint32_t u) { return __builtin_popcount(lt[u]); };
+    // Coordinate descent over the row and column multipliers: each step keeps
+    // the multiplier with the smallest total lifted weight of its row or
+    // column (ties: the smallest element), so the total never increases.
+    for (int round = 0; round < 16; ++round) {
+      bool changed = false;
+      for (int j = 0; j < k; ++j) {
+        uint32_t best = c[j];
+        long best_w = -1;
+        for (uint32_t a = 1; a < q; ++a) {
+          long s = 0;
+          for (int i = 0; i < m; ++i) s += wt(gf_mul(gf_mul(d[i], C[(size_t)i * k + j], p), a, p));
+          if (best_w < 0 || s < best_w) { best_w = s; best = a; }
+        }
+        long cur = 0;
+        for (int i = 0; i < m; ++i) cur += wt(gf_mul(gf_mul(d[i], C[(size_t)i * k + j], p), c[j], p));
+        if (best_w < cur) { c[j] = best; changed = true; }
       }
-      long cur = 0;
-      for (int i = 0; i < m; ++i) cur += wt(gf_mul(gf_mul(d[i], C[(size_t)i * k + j], p), c[j], p));
-      if (best_w < cur) { c[j] = best; changed = true; }
-    }
-    for (int i = 0; i < m; ++i) {
-      uint32_t best = d[i];
-      long best_w = -1;
-      for (uint32_t a = 1; a < q; ++a) {
-        long s = 0;
-        for (int j = 0; j < k; ++j) s += wt(gf_mul(gf_mul(a, C[(size_t)i * k + j], p), c[j], p));
-        if (best_w < 0 || s < best_w) { best_w = s; best = a; }
+      for (int i = 0; i < m; ++i) {
+        uint32_t best = d[i];
+        long best_w = -1;
+        for (uint32_t a = 1; a < q; ++a) {
+          long s = 0;
+          for (int j = 0; j < k; ++j) s += wt(gf_mul(gf_mul(a, C[(size_t)i * k + j], p), c[j], p));
+          if (best_w < 0 || s < best_w) { best_w = s; best = a; }
+        }
+        long cur = 0;
+        for (int j = 0; j < k; ++j) cur += wt(gf_mul(gf_mul(d[i], C[(size_t)i * k + j], p), c[j], p));
+        if (best_w < cur) { d[i] = best; changed = true; }
       }
-      long cur = 0;
-      for (int j = 0; j < k; ++j) cur += wt(gf_mul(gf_mul(d[i], C[(size_t)i * k + j], p), c[j], p));
-      if (best_w < cur) { d[i] = best; changed = true; }
+      if (!changed) break;
     }
-    if (!changed) break;
-  }
-  int total = 0;
-  for (int i = 0; i < m; ++i)
-    for (int j = 0; j < k; ++j) {
-      const uint32_t g = gf_mul(gf_mul(d[i], C[(size_t)i * k + j], p), c[j], p);
-      G[(size_t)i * k + j] = (uint16_t)g;
-      total += wt(g);
-    }
-  if (row_scale)
-    for (int i = 0; i < m; ++i) row_scale[i] = (uint16_t)d[i];
-  if (col_scale)
-    for (int j = 0; j < k; ++j) col_scale[j] = (uint16_t)c[j];
-  if (weight) *weight = total;
-  return PYRIT_OK;
+    int total = 0;
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < k; ++j) {
+        const uint32_t g = gf_mul(gf_mul(d[i], C[(size_t)i * k + j], p), c[j], p);
+        G[(size_t)i * k + j] = (uint16_t)g;
+        total += wt(g);
+      }
+    if (row_scale)
+      for (int i = 0; i < m; ++i) row_scale[i] = (uint16_t)d[i];
+    if (col_scale)
+      for (int j = 0; j < k; ++j) col_scale[j] = (uint16_t)c[j];
+    if (weight) *weight = total;
+    return PYRIT_OK;
+  });
 }
 
 int pyrit_plan_create(int w, int n, uint32_t p, int k, int m, const uint16_t *G,
@@ -296,34 +301,36 @@ int pyrit_plan_create(int w, int n, uint32_t p, int k, int m, const uint16_t *G,
 
 int pyrit_plan_create_ex(int w, int n, uint32_t p, int k, int m, const uint16_t *G, int transform,
                          pyrit_plan **out) {
-  if (transform != PYRIT_TRANSFORM_EMBEDDING && transform != PYRIT_TRANSFORM_PARITY)
-    return PYRIT_EINVAL;
-  if (!out || !G) return PYRIT_EINVAL;
-  *out = nullptr;
-  int rc = pyrit_ring_check(w, n, p);
-  if (rc) return rc;
-  if (k < 1 || k > PYRIT_KMAX || m < 1 || m > PYRIT_MMAX) return PYRIT_EINVAL;
-  if ((uint64_t)k + (uint64_t)m > (1ull << w)) return PYRIT_ETOOLONG;
-  for (int i = 0; i < m * k; ++i)
-    if (G[i] >> w) return PYRIT_ERANGE;
-  pyrit_plan *pl = new (std::nothrow) pyrit_plan();
-  if (!pl) return PYRIT_ENOMEM;
-  pl->w = w;
-  pl->n = n;
-  pl->p = p;
-  pl->k = k;
-  pl->m = m;
-  pl->ring = ring_id(w, n, p, transform);
-  pl->transform = transform;
-  pl->G.assign(G, G + (size_t)m * k);
-  const auto &lt = lift_table(w, n, p);
-  pl->L.resize(pl->G.size());
-  for (size_t i = 0; i < pl->G.size(); ++i) {
-    pl->L[i] = lt[pl->G[i]];
-    pl->weight += __builtin_popcount(pl->L[i]);
-  }
-  *out = pl;
-  return PYRIT_OK;
+  return abi_guard([&]() -> int {
+    if (transform != PYRIT_TRANSFORM_EMBEDDING && transform != PYRIT_TRANSFORM_PARITY)
+      return PYRIT_EINVAL;
+    if (!out || !G) return PYRIT_EINVAL;
+    *out = nullptr;
+    int rc = pyrit_ring_check(w, n, p);
+    if (rc) return rc;
+    if (k < 1 || k > PYRIT_KMAX || m < 1 || m > PYRIT_MMAX) return PYRIT_EINVAL;
+    if ((uint64_t)k + (uint64_t)m > (1ull << w)) return PYRIT_ETOOLONG;
+    for (int i = 0; i < m * k; ++i)
+      if (G[i] >> w) return PYRIT_ERANGE;
+    std::unique_ptr<pyrit_plan> pl(new (std::nothrow) pyrit_plan());
+    if (!pl) return PYRIT_ENOMEM;
+    pl->w = w;
+    pl->n = n;
+    pl->p = p;
+    pl->k = k;
+    pl->m = m;
+    pl->ring = ring_id(w, n, p, transform);
+    pl->transform = transform;
+    pl->G.assign(G, G + (size_t)m * k);
+    const auto &lt = lift_table(w, n, p);
+    pl->L.resize(pl->G.size());
+    for (size_t i = 0; i < pl->G.size(); ++i) {
+      pl->L[i] = lt[pl->G[i]];
+      pl->weight += __builtin_popcount(pl->L[i]);
+    }
+    *out = pl.release();
+    return PYRIT_OK;
+  });
 }
 
 void pyrit_plan_destroy(pyrit_plan *plan) { delete plan; }
@@ -358,20 +365,22 @@ int pyrit_plan_weight(const pyrit_plan *plan, int *weight) {
 
 int pyrit_decode_matrix(const pyrit_plan *plan, const int *erased, int n_erased, int *survivors,
                         uint16_t *D) {
-  if (!plan) return PYRIT_EINVAL;
-  std::shared_ptr<const DecodeEntry> ent;
-  int rc = decode_entry(plan, erased, n_erased, &ent);
-  if (rc) return rc;
-  if (survivors) std::copy(ent->surv.begin(), ent->surv.end(), survivors);
-  if (D) {
-    // rows in the caller's order
-    for (int e = 0; e < n_erased; ++e) {
-      const int row = (int)(std::find(ent->outs.begin(), ent->outs.end(), erased[e]) - ent->outs.begin());
-      std::copy(ent->D.begin() + (size_t)row * plan->k, ent->D.begin() + (size_t)(row + 1) * plan->k,
-                D + (size_t)e * plan->k);
+  return abi_guard([&]() -> int {
+    if (!plan) return PYRIT_EINVAL;
+    std::shared_ptr<const DecodeEntry> ent;
+    int rc = decode_entry(plan, erased, n_erased, &ent);
+    if (rc) return rc;
+    if (survivors) std::copy(ent->surv.begin(), ent->surv.end(), survivors);
+    if (D) {
+      // rows in the caller's order
+      for (int e = 0; e < n_erased; ++e) {
+        const int row = (int)(std::find(ent->outs.begin(), ent->outs.end(), erased[e]) - ent->outs.begin());
+        std::copy(ent->D.begin() + (size_t)row * plan->k, ent->D.begin() + (size_t)(row + 1) * plan->k,
+                  D + (size_t)e * plan->k);
+      }
     }
-  }
-  return PYRIT_OK;
+    return PYRIT_OK;
+  });
 }
 
 }  // extern "C"

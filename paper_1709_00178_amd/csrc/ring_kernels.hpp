@@ -213,15 +213,16 @@ __device__ __forceinline__ void leave_ring(T (&acc)[N]) {
   if constexpr (!PT) reduce_mod_p<W, N, P, T>(acc);
 }
 
-// Load the W slices of one block at this lane's column.  bytes == 0 gives an
+// Load the W slices of one block at this lane's voffset (its column, or
+// kDeadOffset for a lane past the end of the slice).  bytes == 0 gives an
 // empty descriptor: every load is out of range and returns zero without any
 // memory traffic (used for prefetches past the last block).
 template <int W, int V>
 __device__ __forceinline__ void load_block(typename Vec<V>::T (&d)[W], const uint8_t *base,
-                                           uint32_t bytes, uint32_t pitch, uint32_t col) {
+                                           uint32_t bytes, uint32_t pitch, uint32_t voff) {
   const __amdgpu_buffer_rsrc_t r = block_rsrc(base, bytes);
 #pragma unroll
-  for (int t = 0; t < W; ++t) d[t] = bload<V>(r, col, t * pitch);
+  for (int t = 0; t < W; ++t) d[t] = bload<V>(r, voff, t * pitch);
 }
 
 // One lane column of one pass.  Src supplies wave-uniform values:
@@ -249,7 +250,8 @@ __device__ __forceinline__ void code_column(const Src &src, uint32_t col, bool l
   const int k = src.k();
   const uint32_t S = src.S();
   const uint32_t pitch = src.pitch();    // slice stride (>= S)
-  const uint32_t span = (W - 1) * pitch + S;  // bytes of a block holding slices
+  const uint32_t span = block_span(W, S, pitch);  // bytes of a block holding slices
+  const uint32_t voff = lane_load_voffset(col, S);  // dead lanes load nothing
   T acc[MO][N];
 #pragma unroll
   for (int r = 0; r < MO; ++r)
@@ -263,7 +265,7 @@ __device__ __forceinline__ void code_column(const Src &src, uint32_t col, bool l
   T d[2][W];
   auto clampj = [&](int jj) { return jj < k ? jj : k - 1; };
   auto prefetch = [&](int slot, int jj, const uint8_t *base) {
-    load_block<W, V>(d[slot], base, jj < k ? span : 0u, pitch, col);
+    load_block<W, V>(d[slot], base, jj < k ? span : 0u, pitch, voff);
   };
   // Scalar operands run ahead of their use: the block pointer one prefetch
   // ahead and the lifted coefficients one block ahead (one 16-byte scalar
@@ -331,7 +333,7 @@ __device__ __forceinline__ void code_tile(const Src &src, uint32_t col0, uint32_
   const int k = src.k();
   const uint32_t S = src.S();
   const uint32_t pitch = src.pitch();    // slice stride (>= S)
-  const uint32_t span = (W - 1) * pitch + S;  // bytes of a block holding slices
+  const uint32_t span = block_span(W, S, pitch);  // bytes of a block holding slices
   T acc[MO][N];
 #pragma unroll
   for (int r = 0; r < MO; ++r)
@@ -340,9 +342,11 @@ __device__ __forceinline__ void code_tile(const Src &src, uint32_t col0, uint32_
 
   T d[2][W];
   // prefetch of (chunk base cb, block jj); cb >= col1 means past the end
+  // (empty descriptor), and lanes past the end of the slice load nothing
   auto prefetch = [&](int slot, uint32_t cb, int jj) {
     const bool ok = cb < col1;
-    load_block<W, V>(d[slot], src.in(ok ? jj : 0), ok ? span : 0u, pitch, cb + lane * 4u * V);
+    load_block<W, V>(d[slot], src.in(ok ? jj : 0), ok ? span : 0u, pitch,
+                     lane_load_voffset(lane_col(cb, lane, V), S));
   };
   uint32_t cb = col0;  // chunk being accumulated
   int j = 0;           // block being accumulated
@@ -355,7 +359,7 @@ __device__ __forceinline__ void code_tile(const Src &src, uint32_t col0, uint32_
       prefetch(q ^ 1, last ? cb + kChunk : cb, last ? 0 : j + 1);
       accumulate<W, N, P, MO, PT, T>(acc, d[q], src.lift8(j));
       if (last) {
-        const uint32_t col = cb + lane * 4u * V;
+        const uint32_t col = lane_col(cb, lane, V);
         if (col < S) {
 #pragma unroll
           for (int r = 0; r < MO; ++r) {

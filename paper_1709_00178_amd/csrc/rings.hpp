@@ -40,6 +40,38 @@ constexpr int ring_max_out(int ring) {
   return kRings[ring].n <= 9 ? 8 : kRings[ring].n <= 11 ? 6 : 4;
 }
 
+// ---- how a lane addresses a block (kernels and host-side checks share it)
+// A block's w slices start at base + t * pitch (t < w); the block spans
+// (w - 1) * pitch + S bytes.  A lane reads the 4V bytes of its column `col`
+// of slice t through a raw buffer descriptor of `span` records, with
+// voffset = col and soffset = t * pitch.  Lanes whose column lies at or past
+// S code nothing (the last chunk of a slice is often partial); their loads
+// take the voffset kDeadOffset instead.  It exceeds every record count
+// (spans stay below 2^31), so those loads return zero without touching
+// memory whether or not the hardware adds soffset before its range check,
+// and kDeadOffset + soffset still fits in 32 bits.
+constexpr uint32_t kDeadOffset = 0x80000000u;
+constexpr uint32_t block_span(uint32_t w, uint32_t S, uint32_t pitch) {
+  return (w - 1) * pitch + S;
+}
+constexpr uint32_t lane_load_voffset(uint32_t col, uint32_t S) {
+  return col < S ? col : kDeadOffset;
+}
+// Column of lane `lane` (lanes of V dwords) in the chunk of 64 lanes that
+// starts at chunk_base.
+constexpr uint32_t lane_col(uint32_t chunk_base, uint32_t lane, uint32_t V) {
+  return chunk_base + lane * 4u * V;
+}
+// Plain kernel: workgroup b codes the chunk at b * 256 V bytes.
+constexpr uint32_t plain_chunk_base(uint32_t b, uint32_t V) { return b * 64u * 4u * V; }
+// Batch grid kernel: the i-th workgroup of a pass holds `pairs` chunks (one
+// per wave, or per split-K pair of waves); wave `wave` codes chunk
+// i * pairs + wave / ks.
+constexpr uint32_t grid_chunk_base(uint32_t i, uint32_t wave, uint32_t pairs, uint32_t ks,
+                                   uint32_t chunk) {
+  return (i * pairs + wave / ks) * chunk;
+}
+
 // Arguments of one coding pass: outputs out[r] (r < nout) are
 // sum_j lift[j][r] (*) in[j] in the ring, reduced mod p.
 struct PassArgs {

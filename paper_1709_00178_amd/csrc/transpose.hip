@@ -24,6 +24,9 @@ namespace {
 constexpr int kTransposeWG = 256;
 
 // Bit (r, c) of the 8 x 8 matrix whose row r is byte r of x moves to (c, r).
+// The standard three-step delta-swap transpose of an 8 x 8 bit matrix held in
+// one 64-bit word (H. S. Warren, "Hacker's Delight", 2nd ed., Sec. 7-3,
+// transposing a bit matrix): swap 1 x 1, then 2 x 2, then 4 x 4 sub-blocks.
 __device__ __forceinline__ uint64_t transpose8(uint64_t x) {
   uint64_t t;
   t = (x ^ (x >> 7)) & 0x00AA00AA00AA00AAull;
@@ -169,12 +172,22 @@ __global__ __launch_bounds__(kTransposeWG) void from_sliced_kernel(const uint8_t
     stage[wv][i][lane] = x;
   }
   __syncthreads();
-  // coalesced: 16-byte unit e of the wave's span belongs to lane e / (2 BYTES)
-  u32x4 *dst = (u32x4 *)(sym + (size_t)g0 * 32 * BYTES);
+  // coalesced: 16-byte unit e of the wave's span belongs to lane e / (2 BYTES).
+  // Each unit is stored as two 8-byte stores, never one 16-byte store: a
+  // store wider than 64 bits reads its data registers after it issues, and
+  // generated code has been seen to overwrite them in the very next
+  // instruction (here an LDS read of the next unit would be one), corrupting
+  // stored bytes now and then.  The empty asm keeps the halves apart.
+  uint64_t *dst = (uint64_t *)(sym + (size_t)g0 * 32 * BYTES);
 #pragma unroll
   for (int i = 0; i < 2 * BYTES; ++i) {
     const uint32_t e = i * 64 + lane;
-    if (g0 + e / (2 * BYTES) < lanes) dst[e] = stage[wv][e % (2 * BYTES)][e / (2 * BYTES)];
+    if (g0 + e / (2 * BYTES) < lanes) {
+      const u32x4 x = stage[wv][e % (2 * BYTES)][e / (2 * BYTES)];
+      dst[2 * e] = ((uint64_t)x.y << 32) | x.x;
+      __asm__ volatile("" ::: "memory");
+      dst[2 * e + 1] = ((uint64_t)x.w << 32) | x.z;
+    }
   }
 }
 

@@ -84,6 +84,18 @@ def stripe_buffers(st, arena, fill=True):
     return blocks, ins, outs
 
 
+def fill_inputs(stripes, bufs):
+    """Fill the input blocks of many stripes (bufs from stripe_buffers with
+    fill=False) with the generator in one launch."""
+    dst, keys, nrand = [], [], []
+    for st, (blocks, ins, _) in zip(stripes, bufs):
+        for b in ins:
+            dst.append(blocks[b])
+            keys.append(st.key(b))
+            nrand.append(st.nrandom)
+    P.fill_random_blocks(dst, keys, nrand)
+
+
 def stripe_bytes_needed(st):
     n_out = len(st.erased) if st.erased else st.m
     return (st.k + n_out) * ((st.block_len + 255) // 256 * 256)

@@ -6,7 +6,7 @@ import pytest
 import oracle
 import paper_1709_00178_amd as P
 from paper_1709_00178_amd import workloads as W
-from tests.gpu_util import (Arena, gather_cols, oracle_cols, sample_cols, stripe_buffers,
+from tests.gpu_util import (Arena, fill_inputs, gather_cols, oracle_cols, sample_cols, stripe_buffers,
                             stripe_bytes_needed, to_host, torch_mod)
 
 pytestmark = pytest.mark.gpu
@@ -54,7 +54,8 @@ def _check_stripes(stripes, bufs, plans, ncols=16, seed=0):
 
 
 def _build(stripes, plans, arena):
-    bufs = [stripe_buffers(st, arena) for st in stripes]
+    bufs = [stripe_buffers(st, arena, fill=False) for st in stripes]
+    fill_inputs(stripes, bufs)
     items = [(plans.get(st), list(st.erased), bufs[i][0], st.S, st.pitch)
              for i, st in enumerate(stripes)]
     return bufs, items

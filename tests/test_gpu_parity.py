@@ -36,12 +36,46 @@ def test_fill_random_matches_generator():
         assert np.array_equal(got, W.block_bytes(key, nbytes, nrandom))
 
 
-def test_copy_kernel():
-    src = dev_empty(1 << 20)
-    P.fill_random(src, 7)
-    dst = dev_empty(1 << 20)
-    P.copy(dst, src)
-    assert np.array_equal(to_host(dst), to_host(src))
+def test_fill_random_blocks_matches_generator():
+    """Many buffers in one launch (sizes from 8 bytes to several tiles of
+    32 KiB, random prefixes of every length class, an empty buffer), each
+    against the host generator; bytes around each buffer stay untouched."""
+    rng = np.random.Generator(np.random.PCG64(11))
+    sizes = [8, 64, 4096, 32768, 32768 + 8, 3 * 32768 + 1000, 1 << 20, 0, 200000]
+    sizes = [s // 8 * 8 for s in sizes]
+    nrand = [s if i % 3 == 0 else int(rng.integers(0, s + 1)) for i, s in enumerate(sizes)]
+    keys = [int(rng.integers(0, 2**63)) * 2 + 1 for _ in sizes]
+    guard = 256
+    arena = dev_empty(sum(s + 2 * guard for s in sizes))
+    arena.fill_(0xC3)
+    bufs, off = [], 0
+    for s in sizes:
+        bufs.append(arena[off + guard:off + guard + s])
+        off += s + 2 * guard
+    P.fill_random_blocks(bufs, keys, nrand)
+    host = to_host(arena)
+    off = 0
+    for s, nr, key in zip(sizes, nrand, keys):
+        assert np.all(host[off:off + guard] == 0xC3)
+        assert np.array_equal(host[off + guard:off + guard + s], W.block_bytes(key, s, nr)), (s, nr)
+        assert np.all(host[off + guard + s:off + s + 2 * guard] == 0xC3)
+        off += s + 2 * guard
+    with pytest.raises(P.PyritError):
+        P.fill_random_blocks([arena[1:9]], [1])  # not 8-byte aligned
+
+
+@pytest.mark.parametrize("nbytes", [16, 1008, 1024, 1 << 20, (1 << 20) + 48])
+def test_copy_kernel(nbytes):
+    """The copy kernel (16-byte loads, two 8-byte stores per lane) at sizes
+    that end mid-wave and mid-workgroup; the bytes after the copy stay."""
+    src = dev_empty(nbytes)
+    P.fill_random(src, 7 + nbytes)
+    dst = dev_empty(nbytes + 256)
+    dst.fill_(0x5A)
+    P.copy(dst, src, nbytes=nbytes)
+    got = to_host(dst)
+    assert np.array_equal(got[:nbytes], to_host(src))
+    assert np.all(got[nbytes:] == 0x5A)
 
 
 def _full_check(st, G, vec_bytes=0, seed_ids=None):
