@@ -276,8 +276,9 @@ int pyrit_fill_random(uint8_t *dst, size_t nbytes, size_t nrandom, uint64_t key,
 /* pyrit_fill_random for n buffers in one kernel launch: buffer i is
  * dst[i] (device, 8-byte aligned), nbytes[i] bytes (a multiple of 8), filled
  * with the stream of key keys[i], random for bytes < nrandom[i] (nrandom
- * NULL: all bytes) and zero beyond.  The host arrays are copied to a device
- * table that the call allocates and frees; the call returns once the fill
+ * NULL: all bytes) and zero beyond; a buffer of 0 bytes is skipped and its
+ * address may be NULL.  The host arrays are copied to a device table that
+ * the call allocates and frees; the call returns once the fill
  * has completed on `stream`.  Buffers must not overlap.  Errors:
  * PYRIT_EINVAL, PYRIT_ENOMEM, PYRIT_EHIP. */
 int pyrit_fill_random_blocks(uint8_t *const *dst, const size_t *nbytes, const size_t *nrandom,

@@ -236,8 +236,8 @@ int pyrit_fill_random_blocks(uint8_t *const *dst, const size_t *nbytes, const si
     recs.reserve((size_t)n);
     uint64_t tiles = 0;
     for (int i = 0; i < n; ++i) {
+      if (nbytes[i] == 0) continue;  // nothing to fill: the address may be NULL
       if (!dst[i] || nbytes[i] % 8 != 0 || ((uintptr_t)dst[i] & 7u)) return PYRIT_EINVAL;
-      if (nbytes[i] == 0) continue;
       const uint64_t nr = nrandom ? std::min<uint64_t>(nrandom[i], nbytes[i]) : nbytes[i];
       const uint64_t nw = nbytes[i] / 8;
       recs.push_back({(uint64_t)(uintptr_t)dst[i], nw, nr, keys[i], tiles});
