@@ -62,7 +62,8 @@ enum {
   PYRIT_EHIP = -10,        /* a HIP runtime call failed */
   PYRIT_ENOMEM = -11,      /* host or device allocation failed */
   PYRIT_EBUSY = -12,       /* resource cap reached (serving admission) */
-  PYRIT_EINTERNAL = -13    /* an unexpected internal failure (a bug) */
+  PYRIT_EINTERNAL = -13,   /* an unexpected internal failure (a bug) */
+  PYRIT_ETOOBIG = -14      /* work exceeds a fixed-size library buffer */
 };
 
 #define PYRIT_KMAX 64      /* maximum data blocks per stripe */
@@ -383,6 +384,32 @@ void pyrit_batch_destroy(pyrit_batch *batch);
 int pyrit_batch_describe(const pyrit_batch_item *items, int n_items, const pyrit_tune *tune,
                          int *n_passes, int *n_work_items, uint64_t *moved_bytes, int *grid,
                          uint64_t *xcd_bytes);
+
+/* A batch run that allocates nothing: for callers that cannot allocate
+ * device memory (tight serving loops, hosts that forbid hipMalloc).  It
+ * does the work of pyrit_batch_create followed by one
+ * pyrit_batch_launch_direct and pyrit_batch_destroy, with the same outputs,
+ * but the batch's device image (work queue, pass descriptors, pointer and
+ * lift tables, queue counters) goes into a fixed device array of the
+ * library instead of a new allocation.  That array holds
+ * PYRIT_SCRATCH_BYTES bytes on each GPU the library runs on, from the
+ * first call on that GPU until the process ends; a batch whose image is
+ * larger returns PYRIT_ETOOBIG (split its items over several calls).
+ *
+ * Each call builds the image in host memory and copies it into the array on
+ * `stream`, ahead of the kernel (the copy also zeroes the queue counters).
+ * The copy is from pageable host memory, which HIP performs synchronously,
+ * so the call returns after the copy has completed.  Calls on one stream are
+ * ordered.  Every call on one GPU shares that GPU's array, which keeps the
+ * last call's image: calls that overlap on one GPU (from several host
+ * threads, or on several streams whose work may run at the same time) race
+ * on it, and the caller must serialise them.  The current device must be
+ * the stream's device.  A stream that is being captured into a graph is
+ * PYRIT_EINVAL: the captured copy would read host memory the call has
+ * released.  Errors as pyrit_batch_create, plus PYRIT_ETOOBIG. */
+#define PYRIT_SCRATCH_BYTES (8u << 20)
+int pyrit_batch_run_noalloc(const pyrit_batch_item *items, int n_items, const pyrit_tune *tune,
+                            void *stream);
 
 /* ------------------------------------------------------------------ serving
  * A request loop with continuous batching.  Requests arrive over time; each

@@ -14,7 +14,7 @@ import numpy as np
 
 from ._lib import lib
 
-__all__ = ["PyritError", "Plan", "Batch", "ring_check", "ring_supported", "lift", "ring_reduce",
+__all__ = ["PyritError", "Plan", "Batch", "batch_run_noalloc", "ring_check", "ring_supported", "lift", "ring_reduce",
            "ring_mul", "gf_mul", "cauchy", "fill_random", "fill_random_blocks", "copy", "version"]
 
 PYRIT_OK = 0
@@ -269,6 +269,24 @@ def batch_describe(items, mode: str = "grid", tile_bytes: int = 0, grid: int = 0
     del keep
     return {"passes": np_.value, "work_items": ni.value, "moved_bytes": mv.value,
             "grid": gr.value, "xcd_bytes": list(xb)}
+
+
+def batch_run_noalloc(items, mode: str = "grid", tile_bytes: int = 0, grid: int = 0,
+                      wg_threads: int = 0, xcd_order: int = 0, split_k: int = 0,
+                      stream=None) -> None:
+    """One run of a batch of these items without allocating device memory
+    (pyrit_batch_run_noalloc): the batch image goes into the library's fixed
+    per-GPU array of SCRATCH_BYTES bytes.  Items and tuning as `Batch`.
+    Calls that overlap on one GPU race on that array."""
+    items = list(items)
+    arr, keep = _batch_items(items)
+    tune = _batch_tune(mode, tile_bytes, grid, wg_threads, xcd_order, split_k)
+    _check(lib().pyrit_batch_run_noalloc(arr, len(items), ctypes.byref(tune),
+                                         _stream_handle(stream)))
+    del keep
+
+
+SCRATCH_BYTES = 8 << 20  # PYRIT_SCRATCH_BYTES
 
 
 class Batch:

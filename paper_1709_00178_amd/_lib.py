@@ -54,6 +54,7 @@ SIGNATURES = {
     "pyrit_batch_destroy": (None, [c_vp]),
     "pyrit_batch_describe": (c_int, [c_vp, c_int, c_vp, P(c_int), P(c_int), P(c_u64), P(c_int),
                                      P(c_u64)]),
+    "pyrit_batch_run_noalloc": (c_int, [c_vp, c_int, c_vp, c_vp]),
     "pyrit_server_create": (c_int, [c_vp, P(c_vp)]),
     "pyrit_server_pool": (c_vp, [c_vp]),
     "pyrit_server_run": (c_int, [c_vp, c_vp, c_int, c_vp, c_vp]),

@@ -266,3 +266,81 @@ const void *kernel_fn(int mode, int wg, int xcd_order, int split) {
 }
 
 }  // namespace pyrit
+
+// ------------------------------------------------------------------------
+// A batch run without allocation (pyrit_batch_run_noalloc).  The batch image
+// goes into `scratch`, a fixed array of device memory that every call on a
+// GPU shares.  In host code `scratch` names a host-side stand-in, not the
+// array: its device address is looked up once per GPU with
+// hipGetSymbolAddress and only that address is handed to copies and kernels.
+
+#include <mutex>
+
+#include "batch_host.hpp"
+#include "internal.hpp"
+
+namespace pyrit {
+
+static __device__ __align__(256) uint8_t scratch[PYRIT_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices];  // the array's device address per GPU, once looked up
+
+// Device address of the current GPU's scratch array (looked up on the first
+// call on that GPU, with that GPU current).
+int scratch_address(void **out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return PYRIT_EHIP;
+  if (dev < 0 || dev >= kMaxDevices) return PYRIT_EHIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return PYRIT_EHIP;
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return PYRIT_OK;
+}
+
+}  // namespace
+}  // namespace pyrit
+
+extern "C" int pyrit_batch_run_noalloc(const pyrit_batch_item *items, int n_items,
+                                       const pyrit_tune *tune, void *stream) {
+  using namespace pyrit;
+  return abi_guard([&]() -> int {
+    if (n_items < 0 || (n_items > 0 && !items)) return PYRIT_EINVAL;
+    pyrit_tune t{};
+    if (tune) t = *tune;
+    int rc = batch_check_tune(&t);
+    if (rc) return rc;
+    int grid = 0;
+    if (t.mode != kModeGrid) {
+      rc = batch_resident_grid(t, &grid);
+      if (rc) return rc;
+    }
+    // Under stream capture the copy below would become a graph node that
+    // reads the host image after this call has released it.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing((hipStream_t)stream, &cap) != hipSuccess) return PYRIT_EHIP;
+    if (cap != hipStreamCaptureStatusNone) return PYRIT_EINVAL;
+    void *dev = nullptr;
+    rc = scratch_address(&dev);
+    if (rc) return rc;
+    BatchImage bi;
+    rc = build_batch_image(items, n_items, t, grid, (uint64_t)(uintptr_t)dev, &bi);
+    if (rc) return rc;
+    if (bi.n_items == 0) return PYRIT_OK;
+    if (bi.img.size() > (size_t)PYRIT_SCRATCH_BYTES) return PYRIT_ETOOBIG;
+    // From pageable host memory: the copy completes before hipMemcpyAsync
+    // returns, so the host image may be released afterwards.  The image's
+    // counter words are zero, which resets the queue counters of this run.
+    if (hipMemcpyAsync(dev, bi.img.data(), bi.img.size(), hipMemcpyHostToDevice,
+                       (hipStream_t)stream) != hipSuccess)
+      return PYRIT_EHIP;
+    return launch_batch_image(bi, dev, stream);
+  });
+}

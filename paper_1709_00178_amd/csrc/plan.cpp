@@ -177,6 +177,7 @@ const char *pyrit_strerror(int code) {
     case PYRIT_ENOMEM: return "out of memory";
     case PYRIT_EBUSY: return "resource cap reached";
     case PYRIT_EINTERNAL: return "internal error";
+    case PYRIT_ETOOBIG: return "work exceeds a fixed-size library buffer";
     default: return "unknown error";
   }
 }
