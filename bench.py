@@ -263,7 +263,7 @@ def roctx():
     return None
 
 
-def copy_ceiling(moved, stream):
+def copy_rate(moved, stream):
     """GB/s of the library's device copy moving `moved` bytes (half read,
     half written)."""
     import torch
@@ -345,8 +345,10 @@ def bench_c1(args, stream, out, log):
                                      "batched_GBps_moved": round(d_moved / (d_batch * 1e-3) / 1e9, 1),
                                      "plain_ms": round(d_plain, 4), "batched_ms": round(d_batch, 4)}},
     })
-    # device copy of the same byte volume: a bandwidth reference
-    out["copy_ceiling_GBps"] = copy_ceiling(moved, stream)
+    # device copy of the same byte volume: a bandwidth reference with equal
+    # read and write traffic (the encode reads 10 bytes for every 4 it
+    # writes, and HBM writes cost more than reads, so a copy runs below it)
+    out["copy_GBps"] = copy_rate(moved, stream)
     # the C1 stripe under the generalized Cauchy matrix of small lifted weight
     G, _, _, wl = P.cauchy_light(st.w, st.n, st.p, st.k, st.m)
     lplan = P.Plan(st.w, st.n, st.p, st.k, st.m, G=G)
@@ -364,6 +366,17 @@ def bench_c1(args, stream, out, log):
                                  "plain_GBps_moved": round(moved / (lp_ms * 1e-3) / 1e9, 1),
                                  "batched_GBps_moved": round(moved / (lb_ms * 1e-3) / 1e9, 1)}
     del lbatch
+    # ... and under the generalized Cauchy matrix with chosen points
+    Gs, _, _, _, _, ws = P.cauchy_search(st.w, st.n, st.p, st.k, st.m)
+    splan = P.Plan(st.w, st.n, st.p, st.k, st.m, G=Gs)
+    sbatch = P.Batch([(splan, [], blocks, st.S, st.pitch)], **res["batched"]["executor"])
+    for _ in range(3):
+        sbatch.run(stream)
+    sb_ms = min(batch_time_ms(lambda: sbatch.run(stream), 20, stream) for _ in range(3))
+    out["c1"]["generalized_cauchy"] = {
+        "weight": ws, "batched_GBps_moved": round(moved / (sb_ms * 1e-3) / 1e9, 1),
+        "frac_of_peak": round(moved / (sb_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
+    del sbatch
     # two resident C1 stripes encoded in turn: each launch now finds few of
     # its address translations cached, since the two stripes together
     # (1.9 GB) exceed what the per-CU translation caches hold
@@ -468,20 +481,24 @@ def bench_layout(args, stream, out, log):
     torch.cuda.empty_cache()
 
 
-# Outputs per pass of the plain kernel for the rings with n <= 9 (the AOP
-# ring of GF(2^4) and the ESP ring of GF(2^6)): every further pass re-reads
-# the k data blocks.
-PLAIN_OUTPUTS_PER_PASS_N9 = 8
+# Outputs per wave of the plain kernels on the rings with n <= 9 (the AOP
+# ring of GF(2^4) and the ESP ring of GF(2^6)): codes with more parity blocks
+# than this take wide launches (several output groups over one read of the
+# data), or, with 4-byte lanes asked for explicitly, one pass per group.
+PLAIN_OUTPUTS_PER_GROUP_N9 = 8
 
 
 def bench_paper_shapes(args, stream, out, log):
     """The code shapes of the paper's Sec. IV figures, (12,8) over GF(2^4) and
     (60,40), (60,20) over GF(2^6), under the embedding and the parity
-    transform (one plain encode per call; passes of at most eight parity
-    blocks each re-read the data blocks).  At the figures' 1 MiB blocks a
-    launch is a few hundred workgroups and cannot fill the GPU; blocks of
-    about 16 MiB (w slices of S bytes at a pitch of S + 4 KiB) show the same kernels against the HBM
-    roofline, moved bytes counting every pass's re-read of the data."""
+    transform, with the plain Cauchy matrix and the generalized Cauchy
+    matrix of the point search (the paper's codes are generalized Cauchy
+    codes).  At the figures' 1 MiB blocks a launch is a few hundred
+    workgroups and cannot fill the GPU; blocks of about 16 MiB (w slices of
+    S bytes at a pitch of S + 4 KiB) show the same kernels against the HBM
+    roofline on the algorithmic bytes, (k + m) w S: every block read or
+    written once.  `one_pass_per_group` times the same encode as one launch
+    per group of eight parity blocks, each re-reading the data."""
     import torch
 
     import paper_1709_00178_amd as P
@@ -489,29 +506,40 @@ def bench_paper_shapes(args, stream, out, log):
     res = {}
     for (w, n, p), k, m in (((4, 5, 0x1F), 8, 4), ((6, 9, 0x49), 40, 20), ((6, 9, 0x49), 20, 40)):
         row = {"w": w, "k": k, "m": m}
+        Gs = P.cauchy_search(w, n, p, k, m)
+        mats = (("", None), ("generalized_cauchy_", Gs[0]))
+        row["weights"] = {"cauchy": P.Plan(w, n, p, k, m).weight, "generalized_cauchy": Gs[5]}
         # a padded layout holds whole slices: the large block is w * S bytes
         for B, pad in ((1 << 20, 0), (w * W.slice_bytes(16 << 20, w), 4096)):
             st = W.Stripe(w, n, p, k=k, m=m, B=B, seed=W.BASE_SEED + 9, pad=pad)
             arena = Arena(arena_bytes([st], BLOCK_SKEW), BLOCK_SKEW)
             bl = stripe_buffers(st, arena)
-            passes = -(-m // PLAIN_OUTPUTS_PER_PASS_N9)
+            groups = -(-m // PLAIN_OUTPUTS_PER_GROUP_N9)
             moved = (k + m) * w * st.S  # algorithmic: every block read or written once
-            reread = (passes * k + m) * w * st.S  # with each pass re-reading the data
+            reread = (groups * k + m) * w * st.S  # one pass per group re-reads the data
             into = row if B == 1 << 20 else row.setdefault("blocks_16MiB", {"block_bytes": B})
             if B == 1 << 20:
                 row["block_bytes"] = B
             for tr in ("embedding", "parity"):
-                plan = P.Plan(w, n, p, k, m, transform=tr)
-                fn = lambda: plan.encode(bl[:k], bl[k:], st.S, stream=stream, pitch=st.pitch)
-                fn()
-                ms = min(batch_time_ms(fn, 10, stream) for _ in range(2))
-                r = {"GBps_data": round(k * B / (ms * 1e-3) / 1e9, 1), "ms": round(ms, 4)}
-                if B != 1 << 20:
-                    r["GBps_moved"] = round(moved / (ms * 1e-3) / 1e9, 1)
-                    r["frac_of_peak"] = round(moved / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
-                    r["passes"] = passes
-                    r["GBps_with_pass_rereads"] = round(reread / (ms * 1e-3) / 1e9, 1)
-                into[tr] = r
+                for prefix, G in mats:
+                    plan = P.Plan(w, n, p, k, m, transform=tr, G=G)
+                    fn = lambda: plan.encode(bl[:k], bl[k:], st.S, stream=stream, pitch=st.pitch)
+                    fn()
+                    ms = min(batch_time_ms(fn, 10, stream) for _ in range(2))
+                    r = {"GBps_data": round(k * B / (ms * 1e-3) / 1e9, 1), "ms": round(ms, 4)}
+                    if B != 1 << 20:
+                        r["GBps_moved"] = round(moved / (ms * 1e-3) / 1e9, 1)
+                        r["frac_of_peak"] = round(moved / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
+                        if groups > 1:
+                            fp = lambda: plan.encode(bl[:k], bl[k:], st.S, stream=stream,
+                                                     pitch=st.pitch, vec_bytes=4)
+                            fp()
+                            pms = min(batch_time_ms(fp, 10, stream) for _ in range(2))
+                            r["one_pass_per_group"] = {
+                                "passes": groups, "ms": round(pms, 4),
+                                "frac_of_peak": round(moved / (pms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                                "GBps_with_rereads": round(reread / (pms * 1e-3) / 1e9, 1)}
+                    into[prefix + tr] = r
             del arena, bl
             torch.cuda.empty_cache()
         res[f"({k + m},{k}) GF(2^{w})"] = row

@@ -124,6 +124,25 @@ int pyrit_cauchy_light(int w, int n, uint32_t p, int k, int m, uint16_t *G, uint
                        uint16_t *col_scale, int *weight);
 
 /* -------------------------------------------------------------------- plans */
+/* Generalized Cauchy parity matrix with its points chosen as well (the
+ * generalized Cauchy codes of Sec. III; Sec. II-B: fewer ones in the lifted
+ * matrix mean fewer XORs):
+ *   G[i*k + j] = row_scale[i] * col_scale[j] / (X[i] + Y[j]),
+ * X (m points) and Y (k points) distinct elements of GF(2^w).  Start: X =
+ * {0..m-1}, Y = {m..m+k-1} and the multipliers of pyrit_cauchy_light.  Each
+ * sweep offers every point, in turn, every field element not in use, taking
+ * it (with that row's or column's best multiplier) when the total lifted
+ * weight drops, then re-chooses all multipliers by coordinate descent; it
+ * stops after `sweeps` sweeps or a sweep without a gain.  Any distinct
+ * points and nonzero multipliers give a Cauchy matrix scaled by rows and
+ * columns, whose square submatrices are all nonsingular: G is MDS.  X, Y,
+ * row_scale, col_scale and weight (the total lifted weight) may be NULL.
+ * Deterministic.  w <= 10 (PYRIT_EUNSUPPORTED above).  Errors as
+ * pyrit_cauchy_light, plus PYRIT_EINVAL for sweeps < 0. */
+int pyrit_cauchy_search(int w, int n, uint32_t p, int k, int m, int sweeps, uint16_t *G,
+                        uint16_t *X, uint16_t *Y, uint16_t *row_scale, uint16_t *col_scale,
+                        int *weight);
+
 typedef struct pyrit_plan pyrit_plan;
 
 /* How data enter and leave the ring.
@@ -286,8 +305,9 @@ int pyrit_fill_random_blocks(uint8_t *const *dst, const size_t *nbytes, const si
                              const uint64_t *keys, int n, void *stream);
 
 /* Device-to-device copy with the library's streaming copy kernel (16-byte
- * non-temporal loads, stores with the coding kernels' SC1 policy, as two
- * 8-byte stores); nbytes a multiple of 16.  A bandwidth reference. */
+ * non-temporal loads, each 16 bytes stored as two 8-byte stores with the
+ * default cache policy); src and dst 16-byte aligned, nbytes a multiple of
+ * 16.  A bandwidth reference for equal read and write traffic. */
 int pyrit_copy(uint8_t *dst, const uint8_t *src, size_t nbytes, void *stream);
 
 /* ------------------------------------------------------------------ batches

@@ -15,7 +15,7 @@ import numpy as np
 from ._lib import lib
 
 __all__ = ["PyritError", "Plan", "Batch", "batch_run_noalloc", "ring_check", "ring_supported", "lift", "ring_reduce",
-           "ring_mul", "gf_mul", "cauchy", "fill_random", "fill_random_blocks", "copy", "version"]
+           "ring_mul", "gf_mul", "cauchy", "cauchy_light", "cauchy_search", "fill_random", "fill_random_blocks", "copy", "version"]
 
 PYRIT_OK = 0
 
@@ -85,6 +85,23 @@ def cauchy_light(w: int, n: int, p: int, k: int, m: int):
     _check(lib().pyrit_cauchy_light(w, n, p, k, m, G.ctypes.data, rs.ctypes.data, cs.ctypes.data,
                                     ctypes.byref(wt)))
     return G, rs, cs, wt.value
+
+
+def cauchy_search(w: int, n: int, p: int, k: int, m: int, sweeps: int = 4):
+    """Generalized Cauchy matrix with points and row/column multipliers
+    chosen for a small lifted weight in R_{2,n} (pyrit_cauchy_search):
+    returns (G, X, Y, row_scale, col_scale, weight), G[i][j] =
+    row_scale[i] * col_scale[j] / (X[i] + Y[j])."""
+    G = np.zeros((m, k), dtype=np.uint16)
+    X = np.zeros(m, dtype=np.uint16)
+    Y = np.zeros(k, dtype=np.uint16)
+    rs = np.zeros(m, dtype=np.uint16)
+    cs = np.zeros(k, dtype=np.uint16)
+    wt = ctypes.c_int()
+    _check(lib().pyrit_cauchy_search(w, n, p, k, m, sweeps, G.ctypes.data, X.ctypes.data,
+                                     Y.ctypes.data, rs.ctypes.data, cs.ctypes.data,
+                                     ctypes.byref(wt)))
+    return G, X, Y, rs, cs, wt.value
 
 
 def _dev_ptr(x, need: int = 0) -> int:

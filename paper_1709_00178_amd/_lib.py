@@ -30,6 +30,8 @@ SIGNATURES = {
     "pyrit_gf_mul": (c_int, [c_int, c_u32, c_u32, c_u32, P(c_u32)]),
     "pyrit_cauchy": (c_int, [c_int, c_u32, c_int, c_int, c_vp]),
     "pyrit_cauchy_light": (c_int, [c_int, c_int, c_u32, c_int, c_int, c_vp, c_vp, c_vp, P(c_int)]),
+    "pyrit_cauchy_search": (c_int, [c_int, c_int, c_u32, c_int, c_int, c_int, c_vp, c_vp, c_vp,
+                                    c_vp, c_vp, P(c_int)]),
     "pyrit_plan_create": (c_int, [c_int, c_int, c_u32, c_int, c_int, c_vp, P(c_vp)]),
     "pyrit_plan_create_ex": (c_int, [c_int, c_int, c_u32, c_int, c_int, c_vp, c_int, P(c_vp)]),
     "pyrit_plan_transform": (c_int, [c_vp, P(c_int)]),

@@ -35,8 +35,17 @@ SOURCES = [
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", f"-I{os.path.join(HERE, '..', 'include')}"]
 # Packed-FP32 instructions stay disabled in every device compile.
+# The two LLVM options keep the small fields' fused coefficient bodies (a
+# tree of wave-uniform branches on the coefficient's bits, 2^w leaves per
+# output) in registers: without them the CFG structurizer turns each uniform
+# if/else into a linear flow that keeps every accumulator's old value alive
+# beside its new one (twice the VGPRs), and common-code sinking merges leaf
+# bodies into one indexed by a PHI of array indices (arrays in scratch).
+# Branches that are not wave-uniform are structurized as before.
 HIP_FLAGS = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-             "-fgpu-flush-denormals-to-zero", "-munsafe-fp-atomics"]
+             "-fgpu-flush-denormals-to-zero", "-munsafe-fp-atomics",
+             "-mllvm", "-structurizecfg-skip-uniform-regions=true",
+             "-mllvm", "-simplifycfg-sink-common=false"]
 
 
 def _compile(src: str, verbose: bool) -> str:

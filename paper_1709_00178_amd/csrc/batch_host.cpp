@@ -35,18 +35,18 @@ int item_passes(const pyrit_batch_item &it, std::vector<HostPass> *out, uint64_t
   int rc = check_slices(pl->w, it.slice_bytes, &pitch);
   if (rc) return rc;
   std::vector<int> ins, outs;
-  const uint32_t *L = nullptr;
+  const uint32_t *coef = nullptr;  // coefficient words (coef_words), outputs x k
   std::shared_ptr<const DecodeEntry> ent;
   if (it.n_erased == 0) {
     for (int j = 0; j < pl->k; ++j) ins.push_back(j);
     for (int i = 0; i < pl->m; ++i) outs.push_back(pl->k + i);
-    L = pl->L.data();
+    coef = pl->K.data();
   } else {
     rc = decode_entry(pl, it.erased, it.n_erased, &ent);
     if (rc) return rc;
     ins = ent->surv;
     outs = ent->outs;
-    L = ent->L.data();
+    coef = ent->K.data();
   }
   for (int b : ins) {
     if (!it.blocks[b]) return PYRIT_EINVAL;
@@ -71,7 +71,7 @@ int item_passes(const pyrit_batch_item &it, std::vector<HostPass> *out, uint64_t
     hp.lift.assign((size_t)pl->k * kMaxOut, 0);
     for (int j = 0; j < pl->k; ++j)
       for (uint32_t r = 0; r < hp.nout; ++r)
-        hp.lift[(size_t)j * kMaxOut + r] = L[(size_t)(r0 + r) * pl->k + j];
+        hp.lift[(size_t)j * kMaxOut + r] = coef[(size_t)(r0 + r) * pl->k + j];
     *moved += (uint64_t)(pl->k + hp.nout) * pl->w * it.slice_bytes;
     out->push_back(std::move(hp));
   }

@@ -12,6 +12,23 @@ namespace pyrit {
 
 template <int RING>
 int launch_plain_ring(int nout, int vec_bytes, const PassArgs &a, hipStream_t st);
+template <int RING>
+int launch_wide_ring(int groups, const WideArgs &a, hipStream_t st);
+
+static int launch_wide(int ring, int groups, const WideArgs &a, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  switch (ring) {
+    case 0: return launch_wide_ring<0>(groups, a, st);
+    case 1: return launch_wide_ring<1>(groups, a, st);
+    case 2: return launch_wide_ring<2>(groups, a, st);
+    case 3: return launch_wide_ring<3>(groups, a, st);
+    case 4: return launch_wide_ring<4>(groups, a, st);
+    case 5: return launch_wide_ring<5>(groups, a, st);
+    case 6: return launch_wide_ring<6>(groups, a, st);
+    case 7: return launch_wide_ring<7>(groups, a, st);
+    default: return PYRIT_EUNSUPPORTED;
+  }
+}
 
 int default_vec_bytes(int ring, int nout) {
   // Column bytes per lane of the plain kernel, chosen by measurement on
@@ -49,10 +66,11 @@ int launch_pass(int ring, int nout, int vec_bytes, const PassArgs &a, void *stre
 
 static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
-// Run the passes for `nout` outputs of a lifted k-column matrix L (row r of
-// L belongs to out[r]), at most ring_max_out outputs per pass.
+// Run the passes for `nout` outputs of a k-column matrix of coefficient
+// words (coef_words; row r belongs to out[r]), at most ring_max_out outputs
+// per pass.
 static int run_passes(const pyrit_plan *pl, const uint8_t *const *in, uint8_t *const *out, int nout,
-                      const uint32_t *L, size_t S, size_t pitch, int vec_bytes, void *stream) {
+                      const uint32_t *coef, size_t S, size_t pitch, int vec_bytes, void *stream) {
   PassArgs a;
   std::memset(&a, 0, sizeof(a));
   a.k = (uint32_t)pl->k;
@@ -71,7 +89,7 @@ static int run_passes(const pyrit_plan *pl, const uint8_t *const *in, uint8_t *c
       if (!out[r0 + r]) return PYRIT_EINVAL;
       if (!aligned16(out[r0 + r])) return PYRIT_EALIGN;
       a.out[r] = out[r0 + r];
-      for (int j = 0; j < pl->k; ++j) a.lift[j][r] = L[(size_t)(r0 + r) * pl->k + j];
+      for (int j = 0; j < pl->k; ++j) a.lift[j][r] = coef[(size_t)(r0 + r) * pl->k + j];
     }
     for (int r = cnt; r < kMaxOut; ++r)
       for (int j = 0; j < pl->k; ++j) a.lift[j][r] = 0;
@@ -79,6 +97,71 @@ static int run_passes(const pyrit_plan *pl, const uint8_t *const *in, uint8_t *c
     if (rc) return rc;
   }
   return PYRIT_OK;
+}
+
+// The same outputs in wide launches: each launch codes up to
+// wide_groups_fit groups of up to ring_max_out outputs with one read of the
+// inputs (all arguments in the kernel-argument segment).  The outputs of a
+// launch are spread over its groups as evenly as possible.
+static int run_wide(const pyrit_plan *pl, const uint8_t *const *in, uint8_t *const *out, int nout,
+                    const uint32_t *coef, size_t S, size_t pitch, void *stream) {
+  const int k = pl->k, ring = pl->ring;
+  const int MO = ring_max_out(ring);
+  const int fit = wide_groups_fit(ring, k);
+  const bool words16 = kRings[ring].n <= 16;
+  const uint32_t H = wide_header_words();
+  for (int j = 0; j < k; ++j) {
+    if (!in[j]) return PYRIT_EINVAL;
+    if (!aligned16(in[j])) return PYRIT_EALIGN;
+  }
+  for (int r = 0; r < nout; ++r) {
+    if (!out[r]) return PYRIT_EINVAL;
+    if (!aligned16(out[r])) return PYRIT_EALIGN;
+  }
+  for (int r0 = 0; r0 < nout;) {
+    const int left = nout - r0;
+    const int G = std::min(fit, (left + MO - 1) / MO);
+    const int cnt = std::min(left, G * MO);
+    WideArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.w[0] = (uint64_t)(uint32_t)k | (uint64_t)S << 32;
+    a.w[1] = (uint64_t)pitch | (uint64_t)G << 32;
+    const uint32_t rec0 = H + (uint32_t)k + (uint32_t)(G * MO);  // first record word
+    for (int j = 0; j < k; ++j) a.w[H + j] = (uint64_t)(uintptr_t)in[j];
+    for (int g = 0; g < G; ++g) {
+      const int first = cnt * g / G, n_g = cnt * (g + 1) / G - first;  // 1..MO outputs
+      a.w[2] |= (uint64_t)n_g << (4 * g);
+      for (int r = 0; r < n_g; ++r) {
+        const int o = r0 + first + r;
+        a.w[H + k + g * MO + r] = (uint64_t)(uintptr_t)out[o];
+        for (int j = 0; j < k; ++j) {
+          const uint32_t cw = coef[(size_t)o * k + j];
+          uint8_t *rec = (uint8_t *)&a.w[rec0 + 2 * (g * k + j)];
+          if (words16) {
+            const uint16_t v = (uint16_t)cw;
+            std::memcpy(rec + 2 * r, &v, 2);
+          } else {
+            std::memcpy(rec + 4 * r, &cw, 4);
+          }
+        }
+      }
+    }
+    int rc = launch_wide(ring, G, a, stream);
+    if (rc) return rc;
+    r0 += cnt;
+  }
+  return PYRIT_OK;
+}
+
+// Codes whose outputs need more than one pass take wide launches when at
+// least two output groups fit one launch and the caller left the lane width
+// to the library; otherwise one plain pass per ring_max_out outputs.
+static int run_outputs(const pyrit_plan *pl, const uint8_t *const *in, uint8_t *const *out,
+                       int nout, const uint32_t *coef, size_t S, size_t pitch, int vec_bytes,
+                       void *stream) {
+  if (vec_bytes == 0 && nout > ring_max_out(pl->ring) && wide_groups_fit(pl->ring, pl->k) >= 2)
+    return run_wide(pl, in, out, nout, coef, S, pitch, stream);
+  return run_passes(pl, in, out, nout, coef, S, pitch, vec_bytes, stream);
 }
 
 }  // namespace pyrit
@@ -95,8 +178,8 @@ int pyrit_encode_ex(const pyrit_plan *plan, const uint8_t *const *data, uint8_t 
     if (vec_bytes != 0 && vec_bytes != 4 && vec_bytes != 8 && vec_bytes != 16) return PYRIT_EINVAL;
     int rc = check_slices(plan->w, slice_bytes, &slice_pitch);
     if (rc) return rc;
-    return run_passes(plan, data, parity, plan->m, plan->L.data(), slice_bytes, slice_pitch,
-                      vec_bytes, stream);
+    return run_outputs(plan, data, parity, plan->m, plan->K.data(), slice_bytes, slice_pitch,
+                       vec_bytes, stream);
   });
 }
 
@@ -120,8 +203,8 @@ int pyrit_decode_ex(const pyrit_plan *plan, const int *erased, int n_erased, uin
     uint8_t *out[PYRIT_MMAX];
     for (int j = 0; j < plan->k; ++j) in[j] = blocks[ent->surv[j]];
     for (size_t e = 0; e < ent->outs.size(); ++e) out[e] = blocks[ent->outs[e]];
-    return run_passes(plan, in, out, (int)ent->outs.size(), ent->L.data(), slice_bytes, slice_pitch,
-                      0, stream);
+    return run_outputs(plan, in, out, (int)ent->outs.size(), ent->K.data(), slice_bytes,
+                       slice_pitch, 0, stream);
   });
 }
 
@@ -186,24 +269,69 @@ __global__ __launch_bounds__(256) void fill_blocks_kernel(const FillRec *recs, u
   }
 }
 
-// Device copy with the coding kernels' memory policies: non-temporal 16-byte
-// loads and SC1 stores (the store policy that measured fastest on MI355X).
-// Each wave moves 1 KiB per step through buffer descriptors based at the
-// wave's first 16-byte unit; every 16-byte unit is stored as two 8-byte
-// stores (a wider store reads its data registers after it issues, which
-// generated code has been seen to overwrite before the read).
-__global__ __launch_bounds__(256) void copy_kernel(uint8_t *dst, const uint8_t *src, uint64_t n16) {
+// Device copy: non-temporal 16-byte loads, each 16-byte unit stored as two
+// 8-byte stores with the default cache policy.  (On MI355X a 1:1 copy of
+// 0.9 GiB ran 5.4 TB/s this way, 4.7-5.2 TB/s with non-temporal 8-byte
+// stores and 2.5 TB/s with the coding kernels' SC1 8-byte stores, which
+// suit their 10:4 read/write streams.)
+// A wave copies kCopyUnits x 1 KiB per step, and its loads run one step
+// ahead of its stores: on gfx9-family parts one in-order counter covers
+// loads and stores, so waiting for loads issued after a step's stores would
+// also wait for those stores to complete, while loads issued before them
+// can be awaited alone.  Each step's bytes are addressed through a buffer
+// descriptor of exactly the bytes that remain (none past the last step), so
+// lanes past the end neither load nor store.  Every 16-byte unit is stored
+// as two 8-byte stores (a wider store reads its data registers after it
+// issues, which generated code has been seen to overwrite before the read).
+constexpr uint32_t kCopyUnits = 4;
+constexpr uint64_t kCopyStep = 64u * 16u * kCopyUnits;  // bytes per wave step
+
+__device__ __forceinline__ uint32_t copy_step_bytes(uint64_t s, uint64_t steps, uint64_t nbytes) {
+  if (s >= steps) return 0u;
+  const uint64_t left = nbytes - s * kCopyStep;
+  return (uint32_t)(left < kCopyStep ? left : kCopyStep);
+}
+
+// Load step s into x (nothing, through an empty descriptor, past the end).
+__device__ __forceinline__ void copy_load(dev::u32x4 (&x)[kCopyUnits], const uint8_t *src,
+                                          uint64_t s, uint64_t steps, uint64_t nbytes,
+                                          uint32_t lane) {
+  const __amdgpu_buffer_rsrc_t r =
+      dev::block_rsrc(src + (s < steps ? s * kCopyStep : 0), copy_step_bytes(s, steps, nbytes));
+#pragma unroll
+  for (uint32_t u = 0; u < kCopyUnits; ++u) x[u] = dev::bload<4>(r, (u * 64u + lane) * 16u, 0u);
+}
+
+__device__ __forceinline__ void copy_store(const dev::u32x4 (&x)[kCopyUnits], uint8_t *dst,
+                                           uint64_t s, uint64_t steps, uint64_t nbytes,
+                                           uint32_t lane) {
+  const __amdgpu_buffer_rsrc_t r =
+      dev::block_rsrc(dst + s * kCopyStep, copy_step_bytes(s, steps, nbytes));
+#pragma unroll
+  for (uint32_t u = 0; u < kCopyUnits; ++u) dev::bstore<4, 0>(x[u], r, (u * 64u + lane) * 16u, 0u);
+}
+
+__global__ __launch_bounds__(256) void copy_kernel(uint8_t *dst, const uint8_t *src,
+                                                   uint64_t nbytes) {
   const uint32_t lane = threadIdx.x & 63u;
-  const uint64_t stride = (uint64_t)gridDim.x * 256u;
-  for (uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x; i < n16; i += stride) {
-    const uint64_t u0 = i - lane;  // the wave's first unit (the same in every lane)
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u0);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u0 >> 32));
-    const uint64_t off = (((uint64_t)hi << 32) | lo) * 16u;
-    const __amdgpu_buffer_rsrc_t rs = dev::block_rsrc(src + off, 1024u);
-    const __amdgpu_buffer_rsrc_t rd = dev::block_rsrc(dst + off, 1024u);
-    const dev::u32x4 x = dev::bload<4>(rs, lane * 16u, 0u);
-    dev::bstore<4>(x, rd, lane * 16u, 0u);
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint64_t steps = (nbytes + kCopyStep - 1) / kCopyStep;
+  const uint64_t stride = (uint64_t)gridDim.x * 4u;
+  uint64_t s = (uint64_t)blockIdx.x * 4u + wave;
+  if (s >= steps) return;
+  // two register sets in turn: step s + stride is in flight while step s is
+  // stored
+  dev::u32x4 x[kCopyUnits], y[kCopyUnits];
+  copy_load(x, src, s, steps, nbytes, lane);
+  while (true) {
+    copy_load(y, src, s + stride, steps, nbytes, lane);
+    copy_store(x, dst, s, steps, nbytes, lane);
+    s += stride;
+    if (s >= steps) break;
+    copy_load(x, src, s + stride, steps, nbytes, lane);
+    copy_store(y, dst, s, steps, nbytes, lane);
+    s += stride;
+    if (s >= steps) break;
   }
 }
 
@@ -269,9 +397,10 @@ int pyrit_copy(uint8_t *dst, const uint8_t *src, size_t nbytes, void *stream) {
   if (!dst || !src || nbytes % 16 != 0 || ((uintptr_t)dst & 15u) || ((uintptr_t)src & 15u))
     return PYRIT_EINVAL;
   if (nbytes == 0) return PYRIT_OK;
-  const uint64_t n16 = nbytes / 16;
-  hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n16)), dim3(256), 0, (hipStream_t)stream, dst,
-                     src, (uint64_t)n16);
+  const uint64_t steps = (nbytes + kCopyStep - 1) / kCopyStep;  // one per wave
+  const uint64_t wgs = std::min<uint64_t>((steps + 3) / 4, 256ull * 8);
+  hipLaunchKernelGGL(copy_kernel, dim3((unsigned)wgs), dim3(256), 0, (hipStream_t)stream, dst,
+                     src, (uint64_t)nbytes);
   return hipGetLastError() == hipSuccess ? PYRIT_OK : PYRIT_EHIP;
 }
 

@@ -28,8 +28,14 @@ struct DecodeEntry {
   std::vector<int> outs;      // erased block ids, ascending
   std::vector<uint16_t> D;    // outs.size() x k decoding matrix
   std::vector<uint32_t> L;    // lifted D
+  std::vector<uint32_t> K;    // kernel coefficient words of D (coef_words)
   int weight = 0;
 };
+
+// Coefficient words the kernels take for a matrix M (field elements) and its
+// lifted form L: M itself on rings with ring_fused, else L.
+std::vector<uint32_t> coef_words(int ring, const std::vector<uint16_t> &M,
+                                 const std::vector<uint32_t> &L);
 
 // Lifted representative of every field element of a ring (size 2^w).
 const std::vector<uint32_t> &lift_table(int w, int n, uint32_t p);
@@ -61,6 +67,7 @@ struct pyrit_plan {
   int transform = PYRIT_TRANSFORM_EMBEDDING;
   std::vector<uint16_t> G;  // m x k
   std::vector<uint32_t> L;  // m x k lifted
+  std::vector<uint32_t> K;  // m x k kernel coefficient words (coef_words)
   int weight = 0;
   mutable std::mutex mu;
   mutable std::unordered_map<std::string, std::shared_ptr<const pyrit::DecodeEntry>> dcache;

@@ -1,6 +1,7 @@
-// Instantiates the plain kernels of ring 7 (one file per ring: parallel builds).
+// Instantiates the plain and wide kernels of ring 7 (one file per ring: parallel builds).
 #include "plain_impl.hpp"
 
 namespace pyrit {
 template int launch_plain_ring<7>(int, int, const PassArgs &, hipStream_t);
+template int launch_wide_ring<7>(int, const WideArgs &, hipStream_t);
 }

@@ -58,6 +58,12 @@ const std::vector<uint32_t> &lift_table(int w, int n, uint32_t p) {
   return cache.emplace(key, std::move(t)).first->second;
 }
 
+std::vector<uint32_t> coef_words(int ring, const std::vector<uint16_t> &M,
+                                 const std::vector<uint32_t> &L) {
+  if (ring >= 0 && ring_fused(ring)) return std::vector<uint32_t>(M.begin(), M.end());
+  return L;
+}
+
 // Gauss-Jordan inverse of a k x k matrix over GF(2^w) = F_2[x]/(p).
 static int gf_invert(std::vector<uint32_t> &A, int k, uint32_t p) {
   std::vector<uint32_t> I((size_t)k * k, 0);
@@ -149,6 +155,7 @@ int decode_entry(const pyrit_plan *plan, const int *erased, int n_erased,
     ent->L[i] = lt[ent->D[i]];
     ent->weight += __builtin_popcount(ent->L[i]);
   }
+  ent->K = coef_words(plan->ring, ent->D, ent->L);
   std::lock_guard<std::mutex> g(plan->mu);
   auto ins = plan->dcache.emplace(key, ent);
   *out = ins.first->second;
@@ -295,6 +302,161 @@ int pyrit_cauchy_light(int w, int n, uint32_t p, int k, int m, uint16_t *G, uint
   });
 }
 
+namespace {
+
+// GF(2^w) products through logarithm and antilogarithm tables of one
+// generator of the multiplicative group (the smallest element of order
+// 2^w - 1), for the searches below.
+struct GfTables {
+  uint32_t q = 0;
+  std::vector<uint32_t> ex, lg;  // ex[i] = g^i for i < 2(q - 1); lg[g^i] = i
+  GfTables(int w, uint32_t p) : q(1u << w), ex(2 * (size_t)q), lg(q, 0) {
+    uint32_t g = 2;
+    for (;; ++g) {
+      uint32_t x = g, ord = 1;
+      while (x != 1) {
+        x = gf_mul(x, g, p);
+        ++ord;
+      }
+      if (ord == q - 1) break;
+    }
+    uint32_t x = 1;
+    for (uint32_t i = 0; i < 2 * (q - 1); ++i) {
+      ex[i] = x;
+      if (i < q - 1) lg[x] = i;
+      x = gf_mul(x, g, p);
+    }
+  }
+  uint32_t mul(uint32_t a, uint32_t b) const { return a && b ? ex[lg[a] + lg[b]] : 0u; }
+  uint32_t inv(uint32_t a) const { return ex[(q - 1) - lg[a]]; }
+};
+
+}  // namespace
+
+int pyrit_cauchy_search(int w, int n, uint32_t p, int k, int m, int sweeps, uint16_t *G,
+                        uint16_t *X, uint16_t *Y, uint16_t *row_scale, uint16_t *col_scale,
+                        int *weight) {
+  return abi_guard([&]() -> int {
+    int rc = pyrit_ring_check(w, n, p);
+    if (rc) return rc;
+    if (!G || k < 1 || m < 1 || sweeps < 0) return PYRIT_EINVAL;
+    if (w > 10) return PYRIT_EUNSUPPORTED;
+    const uint32_t q = 1u << w;
+    if ((uint64_t)k + (uint64_t)m > q) return PYRIT_ETOOLONG;
+    const GfTables F(w, p);
+    const auto &lt = lift_table(w, n, p);
+    std::vector<int> wt(q);
+    for (uint32_t u = 0; u < q; ++u) wt[u] = __builtin_popcount(lt[u]);
+    std::vector<uint32_t> x(m), y(k), d(m, 1u), c(k, 1u);
+    std::vector<char> used(q, 0);
+    for (int i = 0; i < m; ++i) used[x[i] = (uint32_t)i] = 1;
+    for (int j = 0; j < k; ++j) used[y[j] = (uint32_t)(m + j)] = 1;
+    auto entry = [&](int i, int j) { return F.mul(F.mul(d[i], c[j]), F.inv(x[i] ^ y[j])); };
+    // The multiplier a (a != 0) minimising sum_v wt(a * v) over the values
+    // v; returns that sum.  Ties go to the smallest a.
+    std::vector<uint32_t> vals;
+    auto best_multiplier = [&](uint32_t *a_out) {
+      long best = -1;
+      for (uint32_t a = 1; a < q; ++a) {
+        long s = 0;
+        for (uint32_t v : vals) s += wt[F.mul(a, v)];
+        if (best < 0 || s < best) {
+          best = s;
+          *a_out = a;
+        }
+      }
+      return best;
+    };
+    // Coordinate descent over all multipliers (as pyrit_cauchy_light).
+    auto descend = [&]() {
+      for (int round = 0; round < 16; ++round) {
+        bool changed = false;
+        for (int j = 0; j < k; ++j) {
+          vals.clear();
+          long cur = 0;
+          for (int i = 0; i < m; ++i) {
+            vals.push_back(F.mul(d[i], F.inv(x[i] ^ y[j])));
+            cur += wt[entry(i, j)];
+          }
+          uint32_t a = c[j];
+          if (best_multiplier(&a) < cur) c[j] = a, changed = true;
+        }
+        for (int i = 0; i < m; ++i) {
+          vals.clear();
+          long cur = 0;
+          for (int j = 0; j < k; ++j) {
+            vals.push_back(F.mul(c[j], F.inv(x[i] ^ y[j])));
+            cur += wt[entry(i, j)];
+          }
+          uint32_t a = d[i];
+          if (best_multiplier(&a) < cur) d[i] = a, changed = true;
+        }
+        if (!changed) break;
+      }
+    };
+    descend();
+    for (int sweep = 0; sweep < sweeps; ++sweep) {
+      bool improved = false;
+      // each row point, then each column point, against every unused element
+      for (int i = 0; i < m; ++i) {
+        long cur = 0;
+        for (int j = 0; j < k; ++j) cur += wt[entry(i, j)];
+        for (uint32_t e = 0; e < q; ++e) {
+          if (used[e]) continue;
+          vals.clear();
+          for (int j = 0; j < k; ++j) vals.push_back(F.mul(c[j], F.inv(e ^ y[j])));
+          uint32_t a = 1;
+          const long s = best_multiplier(&a);
+          if (s < cur) {
+            used[x[i]] = 0;
+            used[x[i] = e] = 1;
+            d[i] = a;
+            cur = s;
+            improved = true;
+          }
+        }
+      }
+      for (int j = 0; j < k; ++j) {
+        long cur = 0;
+        for (int i = 0; i < m; ++i) cur += wt[entry(i, j)];
+        for (uint32_t e = 0; e < q; ++e) {
+          if (used[e]) continue;
+          vals.clear();
+          for (int i = 0; i < m; ++i) vals.push_back(F.mul(d[i], F.inv(x[i] ^ e)));
+          uint32_t a = 1;
+          const long s = best_multiplier(&a);
+          if (s < cur) {
+            used[y[j]] = 0;
+            used[y[j] = e] = 1;
+            c[j] = a;
+            cur = s;
+            improved = true;
+          }
+        }
+      }
+      descend();
+      if (!improved) break;
+    }
+    int total = 0;
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < k; ++j) {
+        const uint32_t g = entry(i, j);
+        G[(size_t)i * k + j] = (uint16_t)g;
+        total += wt[g];
+      }
+    for (int i = 0; i < m; ++i) {
+      if (X) X[i] = (uint16_t)x[i];
+      if (row_scale) row_scale[i] = (uint16_t)d[i];
+    }
+    for (int j = 0; j < k; ++j) {
+      if (Y) Y[j] = (uint16_t)y[j];
+      if (col_scale) col_scale[j] = (uint16_t)c[j];
+    }
+    if (weight) *weight = total;
+    return PYRIT_OK;
+  });
+}
+
 int pyrit_plan_create(int w, int n, uint32_t p, int k, int m, const uint16_t *G,
                       pyrit_plan **out) {
   return pyrit_plan_create_ex(w, n, p, k, m, G, PYRIT_TRANSFORM_EMBEDDING, out);
@@ -329,6 +491,7 @@ int pyrit_plan_create_ex(int w, int n, uint32_t p, int k, int m, const uint16_t 
       pl->L[i] = lt[pl->G[i]];
       pl->weight += __builtin_popcount(pl->L[i]);
     }
+    pl->K = coef_words(pl->ring, pl->G, pl->L);
     *out = pl.release();
     return PYRIT_OK;
   });

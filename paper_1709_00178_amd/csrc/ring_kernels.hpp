@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "rings.hpp"
 
 namespace pyrit {
@@ -37,6 +39,18 @@ template <int V> struct Vec;
 template <> struct Vec<1> { typedef uint32_t T; };
 template <> struct Vec<2> { typedef u32x2 T; };
 template <> struct Vec<4> { typedef u32x4 T; };
+
+// f(std::integral_constant<int, I>) for I = B, B+1, ..., E-1: a loop whose
+// index is a compile-time constant in the body without relying on the loop
+// unroller (which gives up on bodies as large as the fused rotations, and
+// would then leave register arrays indexed at run time, i.e. in scratch).
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
 
 // Raw-buffer descriptor word 3 for gfx9-family parts (32-bit data format).
 constexpr int kBufDword3 = 0x00020000;
@@ -62,24 +76,24 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t block_rsrc(const void *base, u
                                            kBufDword3);
 }
 
-template <int V>
+template <int V, int LP = kLoadPolicy>
 __device__ __forceinline__ typename Vec<V>::T bload(__amdgpu_buffer_rsrc_t r, uint32_t voff,
                                                     uint32_t soff) {
   if constexpr (V == 1)
-    return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, kLoadPolicy);
+    return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, LP);
   else if constexpr (V == 2)
-    return __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, kLoadPolicy);
+    return __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, LP);
   else
-    return __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, kLoadPolicy);
+    return __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, LP);
 }
 
-template <int V>
+template <int V, int SP = kStorePolicy>
 __device__ __forceinline__ void bstore(typename Vec<V>::T x, __amdgpu_buffer_rsrc_t r,
                                        uint32_t voff, uint32_t soff) {
   if constexpr (V == 1) {
-    __builtin_amdgcn_raw_buffer_store_b32(x, r, voff, soff, kStorePolicy);
+    __builtin_amdgcn_raw_buffer_store_b32(x, r, voff, soff, SP);
   } else if constexpr (V == 2) {
-    __builtin_amdgcn_raw_buffer_store_b64(x, r, voff, soff, kStorePolicy);
+    __builtin_amdgcn_raw_buffer_store_b64(x, r, voff, soff, SP);
   } else {
     // Two 8-byte stores, not one 16-byte store: a store of more than 64 bits
     // reads its data registers after issue, and the compiler has been seen
@@ -89,9 +103,9 @@ __device__ __forceinline__ void bstore(typename Vec<V>::T x, __amdgpu_buffer_rsr
     // (The empty asm keeps the two halves from being merged back into one
     // 16-byte store.)
     const u32x2 lo = {x.x, x.y}, hi = {x.z, x.w};
-    __builtin_amdgcn_raw_buffer_store_b64(lo, r, voff, soff, kStorePolicy);
+    __builtin_amdgcn_raw_buffer_store_b64(lo, r, voff, soff, SP);
     __asm__ volatile("" ::: "memory");
-    __builtin_amdgcn_raw_buffer_store_b64(hi, r, voff + 8u, soff, kStorePolicy);
+    __builtin_amdgcn_raw_buffer_store_b64(hi, r, voff + 8u, soff, SP);
   }
 }
 
@@ -165,6 +179,89 @@ __device__ __forceinline__ void parity_embed(T (&e)[N], const T (&d)[W]) {
   }
 }
 
+// ---- fused rotations for the small fields (rings with ring_fused) -------
+// Three-input XOR: gfx950's v_bitop3_b32 with truth table 0x96 (the output
+// bit is set where an odd number of the three inputs is set).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+__device__ __forceinline__ u32x2 xor3(u32x2 a, u32x2 b, u32x2 c) {
+  return u32x2{xor3(a.x, b.x, c.x), xor3(a.y, b.y, c.y)};
+}
+__device__ __forceinline__ u32x4 xor3(u32x4 a, u32x4 b, u32x4 c) {
+  return u32x4{xor3(a.x, b.x, c.x), xor3(a.y, b.y, c.y), xor3(a.z, b.z, c.z),
+               xor3(a.w, b.w, c.w)};
+}
+
+constexpr int popc(uint32_t x) {
+  int c = 0;
+  for (; x; x >>= 1) c += (int)(x & 1u);
+  return c;
+}
+// Sparse transform (Sec. II-B) at compile time: among the ring elements
+// u + t p (deg t < N - W), the one of fewest nonzero coefficients, ties
+// going to the smallest integer (the host plan's rule).
+constexpr uint32_t lift_const(uint32_t u, int W, int N, uint32_t P) {
+  uint32_t best = u;
+  int bw = popc(u);
+  for (uint32_t t = 1; t < (1u << (N - W)); ++t) {
+    const uint32_t c = u ^ cl_mul(t, P);
+    const int cw = popc(c);
+    if (cw < bw || (cw == bw && c < best)) {
+      best = c;
+      bw = cw;
+    }
+  }
+  return best;
+}
+
+// The terms of a product by the ring element C, grouped by accumulator:
+// slice term[i][q] (q < cnt[i]) of a WD-slice operand lands on
+// accumulator i.
+template <int WD, int N, uint32_t C>
+struct RotTerms {
+  int cnt[N];
+  int term[N][N];
+  constexpr RotTerms() : cnt(), term() {
+    for (int i = 0; i < N; ++i)
+      for (int s = 0; s < N; ++s) {
+        const int t = (i - s + N) % N;
+        if ((C >> s & 1u) && t < WD) term[i][cnt[i]++] = t;
+      }
+  }
+};
+
+// acc += x^s d for every s set in C (a product by C in R_{2,N}), two terms
+// per instruction: acc[i] = acc[i] ^ d[a] ^ d[b].
+template <int WD, int N, uint32_t C, typename T>
+__device__ __forceinline__ void rot_acc_fused(T (&acc)[N], const T (&d)[WD]) {
+  constexpr RotTerms<WD, N, C> R{};
+  // (constant trip counts, so both loops unroll fully and every index
+  // folds to a constant: the operands stay in registers)
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int q = 0; q < N; q += 2) {
+      if (q + 1 < R.cnt[i]) acc[i] = xor3(acc[i], d[R.term[i][q]], d[R.term[i][q + 1]]);
+      else if (q < R.cnt[i]) acc[i] ^= d[R.term[i][q]];
+    }
+  }
+}
+
+// acc += lift(u) d for a wave-uniform field element u: a scalar branch on
+// each of the W bits of u reaches the body compiled for lift(U), U = u.
+template <int WD, int N, int W, uint32_t P, uint32_t U, int B, typename T>
+__device__ __forceinline__ void acc_field(T (&acc)[N], const T (&d)[WD], uint32_t u) {
+  if constexpr (B == 0) {
+    rot_acc_fused<WD, N, lift_const(U, W, N, P), T>(acc, d);
+  } else {
+    if (u & (1u << (B - 1)))
+      acc_field<WD, N, W, P, U | (1u << (B - 1)), B - 1, T>(acc, d, u);
+    else
+      acc_field<WD, N, W, P, U, B - 1, T>(acc, d, u);
+  }
+}
+
 // acc[(t + s) mod N] ^= d[t] for t < W and every s >= S0 set in c.
 template <int W, int N, int S0, typename T>
 __device__ __forceinline__ void rot_acc(T (&acc)[N], const T (&d)[W], uint32_t c) {
@@ -192,17 +289,26 @@ __device__ __forceinline__ void reduce_mod_p(T (&acc)[N]) {
 
 // One input block into the ring accumulators of MO outputs: embedding
 // transform (the block as is, zero slices implied) or parity transform (the
-// block extended by its parity slices).
+// block extended by its parity slices).  cf holds the coefficient words:
+// field elements for the small fields (N <= 9, fused rotations), lifted
+// ring elements otherwise.
 template <int W, int N, uint32_t P, int MO, bool PT, typename T>
 __device__ __forceinline__ void accumulate(T (&acc)[MO][N], const T (&d)[W], const Lift8 &cf) {
+  constexpr bool kFused = N <= 9;
   if constexpr (PT) {
     T e[N];
     parity_embed<W, N, P, T>(e, d);
-#pragma unroll
-    for (int r = 0; r < MO; ++r) rot_acc<N, N, 0, T>(acc[r], e, cf[r]);
+    static_for<0, MO>([&](auto rc) {
+      constexpr int r = decltype(rc)::value;
+      if constexpr (kFused) acc_field<N, N, W, P, 0, W, T>(acc[r], e, cf[r]);
+      else rot_acc<N, N, 0, T>(acc[r], e, cf[r]);
+    });
   } else {
-#pragma unroll
-    for (int r = 0; r < MO; ++r) rot_acc<W, N, 0, T>(acc[r], d, cf[r]);
+    static_for<0, MO>([&](auto rc) {
+      constexpr int r = decltype(rc)::value;
+      if constexpr (kFused) acc_field<W, N, W, P, 0, W, T>(acc[r], d, cf[r]);
+      else rot_acc<W, N, 0, T>(acc[r], d, cf[r]);
+    });
   }
 }
 
@@ -217,19 +323,20 @@ __device__ __forceinline__ void leave_ring(T (&acc)[N]) {
 // kDeadOffset for a lane past the end of the slice).  bytes == 0 gives an
 // empty descriptor: every load is out of range and returns zero without any
 // memory traffic (used for prefetches past the last block).
-template <int W, int V>
+template <int W, int V, int LP = kLoadPolicy>
 __device__ __forceinline__ void load_block(typename Vec<V>::T (&d)[W], const uint8_t *base,
                                            uint32_t bytes, uint32_t pitch, uint32_t voff) {
   const __amdgpu_buffer_rsrc_t r = block_rsrc(base, bytes);
 #pragma unroll
-  for (int t = 0; t < W; ++t) d[t] = bload<V>(r, voff, t * pitch);
+  for (int t = 0; t < W; ++t) d[t] = bload<V, LP>(r, voff, t * pitch);
 }
 
 // One lane column of one pass.  Src supplies wave-uniform values:
-//   k(), S(), pitch(), nout(), in(j), out(r), lift(j, r) and lift8(j) (the
-//   kMaxOut lifted coefficients of input j, two 16-byte loads); slice t of a block
-//   starts t * pitch() bytes after its base.  Rows r >= nout() must have
-//   zero lifted coefficients; they are neither reduced nor stored.
+//   k(), S(), pitch(), nout(), in(j), out(r) and lift8(j) (the kMaxOut
+//   coefficient words of input j: field elements on the small fields, lifted
+//   ring elements otherwise); slice t of a block starts t * pitch() bytes
+//   after its base.  Rows r >= nout() must have zero coefficient words; they
+//   are neither reduced nor stored.
 //
 // KS = 1: the wave codes every input block of its column chunk.
 // KS = 2 (split-K): a pair of waves of one workgroup shares one column
@@ -241,7 +348,10 @@ __device__ __forceinline__ void load_block(typename Vec<V>::T (&d)[W], const uin
 // Half as many columns are in flight for the same number of waves, which
 // shrinks the set of HBM rows open at once (measured on MI355X: 6.6 -> 7.0
 // TB/s for the 10-in/4-out, 8-slice access pattern).
-template <int W, int N, uint32_t P, int MO, int V, int KS = 1, bool PT = false, class Src>
+// LP: cache policy of the block loads (non-temporal by default; a kernel
+// whose waves share their loads takes the default policy instead).
+template <int W, int N, uint32_t P, int MO, int V, int KS = 1, bool PT = false,
+          int LP = kLoadPolicy, class Src>
 __device__ __forceinline__ void code_column(const Src &src, uint32_t col, bool live,
                                             uint32_t part = 0,
                                             typename Vec<V>::T *xch = nullptr) {
@@ -264,26 +374,29 @@ __device__ __forceinline__ void code_column(const Src &src, uint32_t col, bool l
   // costs occupancy.)
   T d[2][W];
   auto clampj = [&](int jj) { return jj < k ? jj : k - 1; };
-  auto prefetch = [&](int slot, int jj, const uint8_t *base) {
-    load_block<W, V>(d[slot], base, jj < k ? span : 0u, pitch, voff);
+  auto prefetch = [&](T (&dst)[W], int jj, const uint8_t *base) {
+    load_block<W, V, LP>(dst, base, jj < k ? span : 0u, pitch, voff);
   };
   // Scalar operands run ahead of their use: the block pointer one prefetch
   // ahead and the lifted coefficients one block ahead (one 16-byte scalar
   // load), so no scalar-load wait sits between the vector loads and XORs.
-  prefetch(0, (int)part, src.in(clampj((int)part)));
+  prefetch(d[0], (int)part, src.in(clampj((int)part)));
   const uint8_t *ip = src.in(clampj((int)part + KS));
   Lift8 cf = src.lift8(clampj((int)part));
+  // One step: block jq (in register set Q) into the accumulators while block
+  // jq + KS loads into the other set.  The set is a compile-time constant.
+  auto step = [&](auto qc, int jq) {
+    constexpr int q = decltype(qc)::value;
+    prefetch(d[q ^ 1], jq + KS, ip);
+    ip = src.in(clampj(jq + 2 * KS));
+    const Lift8 cn = src.lift8(clampj(jq + KS));
+    accumulate<W, N, P, MO, PT, T>(acc, d[q], cf);
+    cf = cn;
+  };
   for (int j = (int)part; j < k; j += 2 * KS) {
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int jq = j + q * KS;
-      if (jq >= k) break;
-      prefetch(q ^ 1, jq + KS, ip);
-      ip = src.in(clampj(jq + 2 * KS));
-      const Lift8 cn = src.lift8(clampj(jq + KS));
-      accumulate<W, N, P, MO, PT, T>(acc, d[q], cf);
-      cf = cn;
-    }
+    step(std::integral_constant<int, 0>{}, j);
+    if (j + KS >= k) break;
+    step(std::integral_constant<int, 1>{}, j + KS);
   }
 
   if constexpr (KS == 1) {
@@ -343,44 +456,132 @@ __device__ __forceinline__ void code_tile(const Src &src, uint32_t col0, uint32_
   T d[2][W];
   // prefetch of (chunk base cb, block jj); cb >= col1 means past the end
   // (empty descriptor), and lanes past the end of the slice load nothing
-  auto prefetch = [&](int slot, uint32_t cb, int jj) {
+  auto prefetch = [&](T (&dst)[W], uint32_t cb, int jj) {
     const bool ok = cb < col1;
-    load_block<W, V>(d[slot], src.in(ok ? jj : 0), ok ? span : 0u, pitch,
+    load_block<W, V>(dst, src.in(ok ? jj : 0), ok ? span : 0u, pitch,
                      lane_load_voffset(lane_col(cb, lane, V), S));
   };
   uint32_t cb = col0;  // chunk being accumulated
   int j = 0;           // block being accumulated
-  prefetch(0, cb, 0);
-  while (cb < col1) {
+  prefetch(d[0], cb, 0);
+  // One step: block j of chunk cb (in register set Q) into the accumulators
+  // while the next step's block loads into the other set: block j+1 of this
+  // chunk, or block 0 of the next chunk.  False once the tile is done.
+  auto step = [&](auto qc) -> bool {
+    constexpr int q = decltype(qc)::value;
+    const bool last = j + 1 == k;
+    prefetch(d[q ^ 1], last ? cb + kChunk : cb, last ? 0 : j + 1);
+    accumulate<W, N, P, MO, PT, T>(acc, d[q], src.lift8(j));
+    if (!last) {
+      ++j;
+      return true;
+    }
+    const uint32_t col = lane_col(cb, lane, V);
+    if (col < S) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      // next step: block j+1 of this chunk, or block 0 of the next chunk
-      const bool last = j + 1 == k;
-      prefetch(q ^ 1, last ? cb + kChunk : cb, last ? 0 : j + 1);
-      accumulate<W, N, P, MO, PT, T>(acc, d[q], src.lift8(j));
-      if (last) {
-        const uint32_t col = lane_col(cb, lane, V);
-        if (col < S) {
+      for (int r = 0; r < MO; ++r) {
+        if (r >= src.nout()) break;
+        leave_ring<W, N, P, PT, T>(acc[r]);
+        const __amdgpu_buffer_rsrc_t o = block_rsrc(src.out(r), span);
 #pragma unroll
-          for (int r = 0; r < MO; ++r) {
-            if (r >= src.nout()) break;
-            leave_ring<W, N, P, PT, T>(acc[r]);
-            const __amdgpu_buffer_rsrc_t o = block_rsrc(src.out(r), span);
-#pragma unroll
-            for (int t = 0; t < W; ++t) bstore<V>(acc[r][t], o, col, t * pitch);
-          }
-        }
-#pragma unroll
-        for (int r = 0; r < MO; ++r)
-#pragma unroll
-          for (int i = 0; i < N; ++i) acc[r][i] = (T)0;
-        cb += kChunk;
-        j = 0;
-        if (cb >= col1) break;
-      } else {
-        ++j;
+        for (int t = 0; t < W; ++t) bstore<V>(acc[r][t], o, col, t * pitch);
       }
     }
+#pragma unroll
+    for (int r = 0; r < MO; ++r)
+#pragma unroll
+      for (int i = 0; i < N; ++i) acc[r][i] = (T)0;
+    cb += kChunk;
+    j = 0;
+    return cb < col1;
+  };
+  while (cb < col1) {
+    if (!step(std::integral_constant<int, 0>{})) break;
+    if (!step(std::integral_constant<int, 1>{})) break;
+  }
+}
+
+// ---- wide passes: one read of the inputs for several output groups -----
+// s_waitcnt with vmcnt = N and the other counters at their maxima (gfx9
+// encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// One column chunk (64 lanes x 4 bytes) of a wide pass, coded by the G
+// waves of a workgroup: wave g accumulates its MO outputs from every input
+// block, and the blocks reach the waves through a ring of D stages in LDS
+// (`stage`: D x W x 64 dwords) that the waves fill together, each block
+// loaded from HBM once.  Slice t of block j is loaded by wave t mod G
+// straight into stage j mod D (buffer loads to LDS, no registers held).
+// Block j is awaited at step j: each wave waits until its own loads of
+// block j have completed (its later loads, (D - 2) blocks' worth, may still
+// be in flight), then a barrier makes every wave's part visible; stage
+// (j - 1) mod D, read by every wave before that barrier, is then refilled
+// with block j + D - 1.  Loads past the last block use an empty descriptor
+// (no traffic), so every step issues the same number of loads and the
+// counts awaited are constants.  Lanes past the end of the slice load
+// nothing and store nothing.
+template <int W, int N, uint32_t P, int MO, bool PT, int D, class Src>
+__device__ __forceinline__ void code_column_staged(const Src &src, uint32_t col, uint32_t lane,
+                                                   uint32_t g, uint32_t G, uint32_t *stage) {
+  static_assert((D - 2) * W < 64, "awaited loads must fit vmcnt");
+  typedef uint32_t T;
+  const int k = src.k();
+  const uint32_t S = src.S();
+  const uint32_t pitch = src.pitch();
+  const uint32_t span = block_span(W, S, pitch);
+  const uint32_t voff = lane_load_voffset(col, S);
+  T acc[MO][N];
+#pragma unroll
+  for (int r = 0; r < MO; ++r)
+#pragma unroll
+    for (int i = 0; i < N; ++i) acc[r][i] = 0u;
+
+  auto issue = [&](int jj) {
+    const bool ok = jj < k;
+    const __amdgpu_buffer_rsrc_t r = block_rsrc(src.in(ok ? jj : 0), ok ? span : 0u);
+    uint32_t *base = stage + (uint32_t)(jj % D) * (W * 64u);
+    for (uint32_t t = g; t < (uint32_t)W; t += G)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          r, (__attribute__((address_space(3))) void *)(base + t * 64u), 4, voff, t * pitch, 0, 0);
+  };
+  // slices this wave loads per block
+  const uint32_t n_g = g < (uint32_t)W ? ((uint32_t)W - g + G - 1) / G : 0u;
+  auto wait_block = [&]() {
+    static_for<1, W + 1>([&](auto c) {
+      constexpr int kC = decltype(c)::value;
+      if (n_g == (uint32_t)kC) wait_vmcnt<(D - 2) * kC>();
+    });
+  };
+  for (int jj = 0; jj < D - 1; ++jj) issue(jj);
+  Lift8 cf = src.lift8(0);
+  for (int j = 0; j < k; ++j) {
+    wait_block();
+    // (the empty asm statements keep the compiler from moving LDS reads
+    // across the barrier, which it does not see as a memory operation)
+    __asm__ volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    __asm__ volatile("" ::: "memory");
+    issue(j + D - 1);
+    const Lift8 cn = src.lift8(j + 1 < k ? j + 1 : j);
+    const uint32_t *blk = stage + (uint32_t)(j % D) * (W * 64u) + lane;
+    T d[W];
+#pragma unroll
+    for (int t = 0; t < W; ++t) d[t] = blk[t * 64];
+    accumulate<W, N, P, MO, PT, T>(acc, d, cf);
+    cf = cn;
+  }
+  if (col >= S) return;
+#pragma unroll
+  for (int r = 0; r < MO; ++r) {
+    if (r >= src.nout()) break;
+    leave_ring<W, N, P, PT, T>(acc[r]);
+    const __amdgpu_buffer_rsrc_t o = block_rsrc(src.out(r), span);
+#pragma unroll
+    for (int t = 0; t < W; ++t) bstore<1>(acc[r][t], o, col, t * pitch);
   }
 }
 

@@ -40,6 +40,14 @@ constexpr int ring_max_out(int ring) {
   return kRings[ring].n <= 9 ? 8 : kRings[ring].n <= 11 ? 6 : 4;
 }
 
+// Rings whose kernels take each coefficient as its field element u rather
+// than its lifted ring element: the kernel branches on the w bits of u to a
+// body compiled for lift(u) (2^w bodies per output, so only for small
+// fields), in which the terms that land on one accumulator are summed two
+// at a time by three-input XORs.  Other rings take the lifted element c and
+// branch on its n bits, one rotation per set bit.
+constexpr bool ring_fused(int ring) { return kRings[ring].n <= 9; }
+
 // ---- how a lane addresses a block (kernels and host-side checks share it)
 // A block's w slices start at base + t * pitch (t < w); the block spans
 // (w - 1) * pitch + S bytes.  A lane reads the 4V bytes of its column `col`
@@ -73,14 +81,48 @@ constexpr uint32_t grid_chunk_base(uint32_t i, uint32_t wave, uint32_t pairs, ui
 }
 
 // Arguments of one coding pass: outputs out[r] (r < nout) are
-// sum_j lift[j][r] (*) in[j] in the ring, reduced mod p.
+// sum_j coef[j][r] (*) in[j] in the ring, reduced mod p.  A coefficient word
+// is the field element (rings with ring_fused) or its lifted ring element.
 struct PassArgs {
   const uint8_t *in[PYRIT_KMAX];
   uint8_t *out[kMaxOut];
-  uint32_t lift[PYRIT_KMAX][kMaxOut];
+  uint32_t lift[PYRIT_KMAX][kMaxOut];  // coefficient words
   uint32_t k;
   uint32_t S;      // column bytes per slice
   uint32_t pitch;  // bytes from one slice to the next (>= S)
 };
+
+}  // namespace pyrit
+
+namespace pyrit {
+
+// ---- wide passes: codes with more outputs than one pass holds ----------
+// One launch codes G output groups of up to ring_max_out outputs each; the G
+// waves of a workgroup share one column chunk, wave g coding group g, and
+// each input block is fetched from HBM once per launch into LDS, where every
+// wave reads it.  Everything travels in the kernel-argument segment, packed
+// into kWideWords 8-byte words:
+//   word 0: k | S << 32;  word 1: pitch | groups << 32;
+//   word 2: the number of outputs of group g (1..8) in bits 4g..4g+3;
+//   words 3..3+k: input pointers;
+//   then G x ring_max_out output pointers (group g's at g * ring_max_out);
+//   then G x k records of 16 bytes, (g, j) at (g * k + j): the coefficient
+//   words of input j for group g's outputs, as 16-bit words (n <= 16, up to
+//   eight outputs) or 32-bit words (n = 17, four outputs).
+constexpr int kWideWords = 500;         // 4000 bytes of kernel arguments
+constexpr int kWideMaxGroups = 8;       // waves per workgroup
+struct WideArgs {
+  uint64_t w[kWideWords];
+};
+constexpr int wide_header_words() { return 3; }
+// Blocks staged in LDS per workgroup of a wide pass (D stages of w slices x
+// 256 bytes: 8 KiB to 15 KiB).
+constexpr int wide_stages(int ring) { return kRings[ring].w <= 6 ? 8 : 6; }
+// Output groups that fit one launch of a k-input code on `ring`.
+constexpr int wide_groups_fit(int ring, int k) {
+  const int per_group = ring_max_out(ring) + 2 * k;  // pointer words + record words
+  const int g = (kWideWords - wide_header_words() - k) / per_group;
+  return g < kWideMaxGroups ? g : kWideMaxGroups;
+}
 
 }  // namespace pyrit

@@ -92,6 +92,18 @@ int main() {
   int weight = 0;
   CHECK(pyrit_cauchy_light(8, 17, 0x139, 10, 4, G.data(), rs.data(), cs.data(), &weight) == PYRIT_OK);
   CHECK(weight > 0 && weight <= 92);
+  // the point search (a wide GF(2^6) code and the GF(2^10) code)
+  {
+    std::vector<uint16_t> Gs(20 * 40), X(20), Y(40), r2(20), c2(40);
+    int ws = 0;
+    CHECK(pyrit_cauchy_search(6, 9, 0x49, 40, 20, 2, Gs.data(), X.data(), Y.data(), r2.data(),
+                              c2.data(), &ws) == PYRIT_OK);
+    CHECK(ws > 0);
+    CHECK(pyrit_cauchy_search(10, 11, 0x7FF, 16, 4, 1, Gs.data(), nullptr, nullptr, nullptr,
+                              nullptr, &ws) == PYRIT_OK);
+    CHECK(pyrit_cauchy_search(10, 11, 0x7FF, 16, 4, -1, Gs.data(), nullptr, nullptr, nullptr,
+                              nullptr, nullptr) == PYRIT_EINVAL);
+  }
   // error paths
   CHECK(pyrit_ring_check(8, 16, 0x139) != PYRIT_OK);
   CHECK(pyrit_ring_check(8, 17, 0x13B) != PYRIT_OK);

@@ -617,6 +617,46 @@ def test_wide_passes_encode_and_decode(w, n, p, k, m, transform):
         assert np.array_equal(to_host(dev[e]), code[e]), (er, e)
 
 
+# Wide launches: outputs beyond one pass are coded by G waves sharing one
+# column chunk (G output groups per launch, as many as the kernel arguments
+# hold).  Each case against the oracle, whole blocks, ragged S over several
+# workgroups, and against the one-pass-per-group path (vec_bytes = 4).
+# Cases: three uneven groups in one launch on every ring and transform; the
+# paper's (60,40) and (60,20) shapes; codes whose outputs need several wide
+# launches (k = 64).
+@pytest.mark.parametrize("w,n,p,k,m,transform", [
+    (4, 5, 0x1F, 5, 11, "embedding"), (4, 5, 0x1F, 3, 13, "parity"),
+    (8, 17, 0x139, 9, 11, "embedding"), (8, 17, 0x1D7, 7, 9, "embedding"),
+    (10, 11, 0x7FF, 12, 13, "embedding"), (10, 11, 0x7FF, 11, 17, "parity"),
+    (6, 9, 0x49, 40, 20, "embedding"), (6, 9, 0x49, 20, 40, "parity"),
+    (6, 9, 0x49, 20, 40, "embedding"), (10, 11, 0x7FF, 64, 40, "embedding"),
+    (8, 17, 0x139, 64, 14, "embedding")])
+def test_wide_launches_match_oracle_and_passes(w, n, p, k, m, transform):
+    torch = torch_mod()
+    st = W.Stripe(w, n, p, k=k, m=m, B=RAGGED_S * w - 24, stripe=k * 100 + m, seed=43)
+    assert st.S == RAGGED_S
+    plan = P.Plan(w, n, p, k, m, transform=transform)
+    f = oracle.Field(w, p)
+    host = [W.block_bytes(st.key(j), st.block_len, st.B) for j in range(k)]
+    if transform == "parity":
+        want = oracle.encode_parity_transform(f, n, plan.G, host, st.S)
+    else:
+        want = f.encode(plan.G, host, st.S, nthreads=8)
+    data = [torch.from_numpy(h).cuda() for h in host]
+    wide = [dev_empty(st.block_len) for _ in range(m)]
+    passes = [dev_empty(st.block_len) for _ in range(m)]
+    for a, b in zip(wide, passes):
+        a.fill_(0x3C)
+        b.fill_(0xC3)
+    plan.encode(data, wide, st.S)
+    plan.encode(data, passes, st.S, vec_bytes=4)
+    sync()
+    for i in range(m):
+        got = to_host(wide[i])
+        assert np.array_equal(got, want[i]), (i, np.flatnonzero(got != want[i])[:8])
+        assert torch.equal(wide[i], passes[i]), i
+
+
 def test_one_plan_on_concurrent_streams():
     """One plan coding on four streams at once: each stream encodes its own
     copy of the data and decodes its own erasure pattern (the decode cache

@@ -281,10 +281,66 @@ def test_cauchy_light_is_mds(ring, k, m):
         mats = []
 
 
-def test_cauchy_light_decodes_every_pattern_c0_and_c1():
+# Generalized Cauchy with chosen points.  Pins: the entries are exactly
+# row_scale[i] * col_scale[j] / (X[i] + Y[j]) by the oracle's field (a Cauchy
+# matrix scaled by rows and columns, over distinct points), nonsingular
+# square submatrices by schoolbook elimination on small codes, the weight
+# against popcounts of the lifted entries, and recovery by the oracle.
+SEARCH = [((4, 5, 0x1F), 8, 4), ((8, 17, 0x139), 10, 4), ((10, 11, 0x7FF), 16, 4),
+          ((6, 9, 0x49), 40, 20), ((6, 9, 0x49), 20, 40), ((8, 17, 0x1D7), 6, 3)]
+
+
+@pytest.mark.parametrize("ring,k,m", SEARCH, ids=[f"{r[0]}-{k}-{m}" for r, k, m in SEARCH])
+def test_cauchy_search_structure_and_weight(ring, k, m):
+    w, n, p = ring
+    G, X, Y, rs, cs, W_ = P.cauchy_search(w, n, p, k, m)
+    G2, X2, Y2, _, _, W2 = P.cauchy_search(w, n, p, k, m)
+    assert np.array_equal(G, G2) and np.array_equal(X, X2) and W_ == W2  # deterministic
+    pts = [int(v) for v in X] + [int(v) for v in Y]
+    assert len(set(pts)) == k + m and max(pts) < (1 << w)
+    assert (rs != 0).all() and (cs != 0).all()
+    f = oracle.Field(w, p)
+    for i in range(m):
+        for j in range(k):
+            want = f.mul(f.mul(int(rs[i]), int(cs[j])), f.inv(int(X[i]) ^ int(Y[j])))
+            assert int(G[i, j]) == want, (i, j)
+    lifted = [P.lift(w, n, p, int(g)) for g in G.ravel()]
+    assert W_ == sum(bin(c).count("1") for c in lifted)
+    assert W_ <= P.cauchy_light(w, n, p, k, m)[3]
+    assert P.Plan(w, n, p, k, m, G=G).weight == W_
+    # no sweep: the point sets stay {0..m-1} and {m..m+k-1}
+    G0, X0, Y0, *_ = P.cauchy_search(w, n, p, k, m, sweeps=0)
+    assert list(X0) == list(range(m)) and list(Y0) == list(range(m, m + k))
+
+
+@pytest.mark.parametrize("ring,k,m", [((4, 5, 0x1F), 8, 4), ((8, 17, 0x139), 10, 4),
+                                      ((6, 9, 0x49), 6, 3)])
+def test_cauchy_search_is_mds(ring, k, m):
+    w, n, p = ring
+    G = P.cauchy_search(w, n, p, k, m)[0]
+    for s in range(1, m + 1):
+        mats = [G[np.ix_(rows, cols)] for rows in itertools.combinations(range(m), s)
+                for cols in itertools.combinations(range(k), s)]
+        assert sb.det_nonzero_all(mats, w, p).all(), s
+
+
+def test_cauchy_search_errors():
+    with pytest.raises(P.PyritError) as e:
+        P.cauchy_search(4, 5, 0x1F, 12, 5)  # 17 points in GF(16)
+    assert e.value.code == -4
+    with pytest.raises(P.PyritError) as e:
+        P.cauchy_search(4, 5, 0x1F, 4, 2, sweeps=-1)
+    assert e.value.code == -1
+    with pytest.raises(P.PyritError) as e:
+        P.cauchy_search(4, 5, 0x1B, 4, 2)  # not the ring's polynomial
+    assert e.value.code < 0
+
+
+@pytest.mark.parametrize("make", [P.cauchy_light, P.cauchy_search], ids=["light", "search"])
+def test_generalized_cauchy_decodes_every_pattern_c0_and_c1(make):
     for st, pats in [(W.c0(), [c for s in (1, 2) for c in itertools.combinations(range(6), s)]),
                      (W.c1(), list(itertools.combinations(range(14), 4))[::7])]:
-        G = P.cauchy_light(st.w, st.n, st.p, st.k, st.m)[0]
+        G = make(st.w, st.n, st.p, st.k, st.m)[0]
         f = oracle.Field(st.w, st.p)
         rng = np.random.Generator(np.random.PCG64(5))
         S = 64
