@@ -32,12 +32,15 @@ ERRORS = {0: "ok", -1: "invalid argument", -2: "modulus not irreducible",
 
 def build(verbose: bool = False) -> str:
     """Compile the oracle with gcc (-O2, OpenMP, no intrinsics)."""
+    # a temporary name of this process's own, so that builds running at the
+    # same time (parallel test workers) each replace the library whole
+    tmp = f"{_LIB_PATH}.tmp{os.getpid():x}"
     cmd = ["gcc", "-O2", "-fopenmp", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
-           f"-DOR_MUTANT={_MUTANT}", _SRC, "-o", _LIB_PATH + ".tmp"]
+           f"-DOR_MUTANT={_MUTANT}", _SRC, "-o", tmp]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
 
