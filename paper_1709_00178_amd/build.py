@@ -41,11 +41,15 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", f"-I{os.path.join(HERE, '..', '
 # if/else into a linear flow that keeps every accumulator's old value alive
 # beside its new one (twice the VGPRs), and common-code sinking merges leaf
 # bodies into one indexed by a PHI of array indices (arrays in scratch).
-# Branches that are not wave-uniform are structurized as before.
+# Branches that are not wave-uniform are structurized as before.  The third
+# option turns off GVN's memory-dependence queries, which took most of the
+# compile time of those large bodies (minutes per kernel) and changed no
+# instruction of the generated code.
 HIP_FLAGS = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-fgpu-flush-denormals-to-zero", "-munsafe-fp-atomics",
              "-mllvm", "-structurizecfg-skip-uniform-regions=true",
-             "-mllvm", "-simplifycfg-sink-common=false"]
+             "-mllvm", "-simplifycfg-sink-common=false",
+             "-mllvm", "-enable-gvn-memdep=false"]
 
 
 def _compile(src: str, verbose: bool) -> str:

@@ -99,14 +99,15 @@ static int run_passes(const pyrit_plan *pl, const uint8_t *const *in, uint8_t *c
   return PYRIT_OK;
 }
 
-// The same outputs in wide launches: each launch codes up to
+// The same outputs in wide launches: each launch codes 2 to
 // wide_groups_fit groups of up to ring_max_out outputs with one read of the
 // inputs (all arguments in the kernel-argument segment).  The outputs of a
-// launch are spread over its groups as evenly as possible.
+// launch are spread over its groups as evenly as possible; a last group
+// alone takes a plain pass.
 static int run_wide(const pyrit_plan *pl, const uint8_t *const *in, uint8_t *const *out, int nout,
                     const uint32_t *coef, size_t S, size_t pitch, void *stream) {
   const int k = pl->k, ring = pl->ring;
-  const int MO = ring_max_out(ring);
+  const int MO = wide_max_out(ring);
   const int fit = wide_groups_fit(ring, k);
   const bool words16 = kRings[ring].n <= 16;
   const uint32_t H = wide_header_words();
@@ -120,6 +121,8 @@ static int run_wide(const pyrit_plan *pl, const uint8_t *const *in, uint8_t *con
   }
   for (int r0 = 0; r0 < nout;) {
     const int left = nout - r0;
+    if (left <= ring_max_out(ring))  // one pass left: the plain kernel (split-K) codes it
+      return run_passes(pl, in, out + r0, left, coef + (size_t)r0 * k, S, pitch, 0, stream);
     const int G = std::min(fit, (left + MO - 1) / MO);
     const int cnt = std::min(left, G * MO);
     WideArgs a;

@@ -23,6 +23,8 @@ __global__ __launch_bounds__(kPlainWG) void plain_pass_kernel(const PassArgs a) 
 // Wide pass: workgroup b = G waves on the column chunk at b * 256 bytes
 // (4-byte lanes); wave g codes output group g from every input block, the
 // blocks staged once per workgroup in LDS (code_column_staged).
+#define PYRIT_AS4 __attribute__((address_space(4)))
+
 struct WideSrc {
   const WideArgs &a;
   uint32_t g;  // this wave's output group
@@ -32,53 +34,76 @@ struct WideSrc {
   __device__ uint32_t pitch() const { return (uint32_t)a.w[1]; }
   __device__ uint32_t groups() const { return (uint32_t)(a.w[1] >> 32); }
   __device__ int nout() const { return (int)((a.w[2] >> (4 * g)) & 15u); }
-  __device__ const uint8_t *in(int j) const { return (const uint8_t *)a.w[kH + j]; }
+  // the input addresses (read up to k + D - 2 words on: output pointers and
+  // records, all inside the argument block)
+  __device__ const PYRIT_AS4 uint64_t *in_words() const {
+    return (const PYRIT_AS4 uint64_t *)&a.w[kH];
+  }
   template <int MO>
   __device__ uint8_t *out_of(int r) const {
     return (uint8_t *)a.w[kH + k() + g * MO + r];
   }
   template <int MO>
-  __device__ dev::u32x4 record(int j) const {
-    const uint32_t at = kH + k() + groups() * MO + 2 * (g * (uint32_t)k() + j);
-    return *(const dev::u32x4 *)&a.w[at];
+  __device__ const PYRIT_AS4 dev::u32x4 *records_of() const {
+    return (const PYRIT_AS4 dev::u32x4 *)&a.w[kH + k() + groups() * MO + 2 * g * (uint32_t)k()];
   }
 };
-
 template <int MO, bool WORDS16>
 struct WideGroupSrc : WideSrc {
+  // 16-bit words: odd rows read their coefficient from the high half of the
+  // 32-bit word in place (accumulate's HI16)
+  static constexpr bool kHi16 = WORDS16;
   __device__ uint8_t *out(int r) const { return out_of<MO>(r); }
-  __device__ dev::Lift8 lift8(int j) const {
-    const dev::u32x4 x = record<MO>(j);
+  __device__ const PYRIT_AS4 dev::u32x4 *records() const { return records_of<MO>(); }
+  __device__ dev::Lift8 unpack(dev::u32x4 x) const {
     if constexpr (WORDS16) {
-      return dev::Lift8{dev::u32x4{x.x & 0xFFFFu, x.x >> 16, x.y & 0xFFFFu, x.y >> 16},
-                        dev::u32x4{x.z & 0xFFFFu, x.z >> 16, x.w & 0xFFFFu, x.w >> 16}};
+      return dev::Lift8{dev::u32x4{x.x & 0xFFFFu, x.x, x.y & 0xFFFFu, x.y},
+                        dev::u32x4{x.z & 0xFFFFu, x.z, x.w & 0xFFFFu, x.w}};
     } else {
       return dev::Lift8{x, dev::u32x4{0u, 0u, 0u, 0u}};
     }
   }
 };
 
+// NG = ceil(w / G): the slices each wave loads per block.  The embedding
+// transform on the ring (6,9) asks for eight waves per SIMD (at most 64
+// VGPRs), which its six outputs per wave fit.
 template <int RING>
-__global__ __launch_bounds__(64 * kWideMaxGroups) void wide_pass_kernel(const WideArgs a) {
+constexpr int wide_min_waves() {
+  return (kRings[RING].n == 9 && !kRings[RING].parity) ? 8 : 1;
+}
+template <int RING, int NG>
+__global__ __launch_bounds__(64 * kWideMaxGroups)
+__attribute__((amdgpu_waves_per_eu(wide_min_waves<RING>()))) void wide_pass_kernel(const WideArgs a) {
   constexpr RingDesc R = kRings[RING];
-  constexpr int MO = ring_max_out(RING);
+  constexpr int MO = wide_max_out(RING);
   constexpr int D = wide_stages(RING);
-  __shared__ uint32_t stage[D * R.w * 64];
+  __shared__ uint32_t stage[(D * R.w + 1) * 64];
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t G = blockDim.x >> 6;
   const WideGroupSrc<MO, (R.n <= 16)> src{{a, g}};
   const uint32_t col = lane_col(plain_chunk_base(blockIdx.x, 1), lane, 1);
-  dev::code_column_staged<R.w, R.n, R.p, MO, R.parity, D>(src, col, lane, g, G, stage);
+  dev::code_column_staged<R.w, R.n, R.p, MO, R.parity, D, NG>(src, col, lane, g, G, stage);
+}
+
+template <int RING, int NG>
+static int launch_wide_ng(int groups, const WideArgs &a, hipStream_t st) {
+  if constexpr (NG > (kRings[RING].w + 1) / 2) {
+    return PYRIT_EINVAL;
+  } else {
+    if ((kRings[RING].w + groups - 1) / groups != NG) return launch_wide_ng<RING, NG + 1>(groups, a, st);
+    const uint32_t S = (uint32_t)(a.w[0] >> 32);
+    const uint32_t blocks = (S + 255u) / 256u;
+    hipLaunchKernelGGL((wide_pass_kernel<RING, NG>), dim3(blocks), dim3(64 * groups), 0, st, a);
+    return hipGetLastError() == hipSuccess ? PYRIT_OK : PYRIT_EHIP;
+  }
 }
 
 template <int RING>
 int launch_wide_ring(int groups, const WideArgs &a, hipStream_t st) {
-  if (groups < 1 || groups > kWideMaxGroups) return PYRIT_EINVAL;
-  const uint32_t S = (uint32_t)(a.w[0] >> 32);
-  const uint32_t blocks = (S + 255u) / 256u;
-  hipLaunchKernelGGL((wide_pass_kernel<RING>), dim3(blocks), dim3(64 * groups), 0, st, a);
-  return hipGetLastError() == hipSuccess ? PYRIT_OK : PYRIT_EHIP;
+  if (groups < 2 || groups > kWideMaxGroups) return PYRIT_EINVAL;
+  return launch_wide_ng<RING, 1>(groups, a, st);
 }
 
 template <int RING, int MO, int V>

@@ -248,29 +248,37 @@ __device__ __forceinline__ void rot_acc_fused(T (&acc)[N], const T (&d)[WD]) {
   }
 }
 
-// acc += lift(u) d for a wave-uniform field element u: a scalar branch on
-// each of the W bits of u reaches the body compiled for lift(U), U = u.
-template <int WD, int N, int W, uint32_t P, uint32_t U, int B, typename T>
+// acc += lift(u) d for a wave-uniform field element u in [LO, HI): a
+// binary search of scalar compares reaches the body compiled for lift(u).
+// (Each node compares u with its own constant, one s_cmp and one branch on
+// SCC; tests of u's bits, the same at every node of a level, would be
+// computed once up front and kept as 64-bit lane masks, costing an extra
+// scalar AND per node.)
+// SH = 16: u is the high half of the word (the low half is another
+// element's, which the compares u < MID << 16 ignore).
+template <int WD, int N, int W, uint32_t P, uint32_t LO, uint32_t HI, typename T, int SH = 0>
 __device__ __forceinline__ void acc_field(T (&acc)[N], const T (&d)[WD], uint32_t u) {
-  if constexpr (B == 0) {
-    rot_acc_fused<WD, N, lift_const(U, W, N, P), T>(acc, d);
+  if constexpr (HI - LO == 1) {
+    rot_acc_fused<WD, N, lift_const(LO, W, N, P), T>(acc, d);
   } else {
-    if (u & (1u << (B - 1)))
-      acc_field<WD, N, W, P, U | (1u << (B - 1)), B - 1, T>(acc, d, u);
+    constexpr uint32_t MID = (LO + HI) / 2;
+    if (u < (MID << SH))
+      acc_field<WD, N, W, P, LO, MID, T, SH>(acc, d, u);
     else
-      acc_field<WD, N, W, P, U, B - 1, T>(acc, d, u);
+      acc_field<WD, N, W, P, MID, HI, T, SH>(acc, d, u);
   }
 }
 
 // acc[(t + s) mod N] ^= d[t] for t < W and every s >= S0 set in c.
-template <int W, int N, int S0, typename T>
+// (SH: the element sits SH bits up in the word c; the bits below are others'.)
+template <int W, int N, int S0, typename T, int SH = 0>
 __device__ __forceinline__ void rot_acc(T (&acc)[N], const T (&d)[W], uint32_t c) {
   if constexpr (S0 < N) {
-    if (c & (1u << S0)) {
+    if (c & (1u << (S0 + SH))) {
 #pragma unroll
       for (int t = 0; t < W; ++t) acc[(t + S0) % N] ^= d[t];
     }
-    rot_acc<W, N, S0 + 1, T>(acc, d, c);
+    rot_acc<W, N, S0 + 1, T, SH>(acc, d, c);
   }
 }
 
@@ -292,7 +300,11 @@ __device__ __forceinline__ void reduce_mod_p(T (&acc)[N]) {
 // block extended by its parity slices).  cf holds the coefficient words:
 // field elements for the small fields (N <= 9, fused rotations), lifted
 // ring elements otherwise.
-template <int W, int N, uint32_t P, int MO, bool PT, typename T>
+//
+// HI16: the coefficient words of odd rows r are 32-bit words whose high
+// half is the coefficient (two 16-bit coefficients per word, the even row's
+// in the low half, already isolated): they are used without a shift.
+template <int W, int N, uint32_t P, int MO, bool PT, typename T, bool HI16 = false>
 __device__ __forceinline__ void accumulate(T (&acc)[MO][N], const T (&d)[W], const Lift8 &cf) {
   constexpr bool kFused = N <= 9;
   if constexpr (PT) {
@@ -300,14 +312,16 @@ __device__ __forceinline__ void accumulate(T (&acc)[MO][N], const T (&d)[W], con
     parity_embed<W, N, P, T>(e, d);
     static_for<0, MO>([&](auto rc) {
       constexpr int r = decltype(rc)::value;
-      if constexpr (kFused) acc_field<N, N, W, P, 0, W, T>(acc[r], e, cf[r]);
-      else rot_acc<N, N, 0, T>(acc[r], e, cf[r]);
+      constexpr int SH = HI16 && (r & 1) ? 16 : 0;
+      if constexpr (kFused) acc_field<N, N, W, P, 0, (1u << W), T, SH>(acc[r], e, cf[r]);
+      else rot_acc<N, N, 0, T, SH>(acc[r], e, cf[r]);
     });
   } else {
     static_for<0, MO>([&](auto rc) {
       constexpr int r = decltype(rc)::value;
-      if constexpr (kFused) acc_field<W, N, W, P, 0, W, T>(acc[r], d, cf[r]);
-      else rot_acc<W, N, 0, T>(acc[r], d, cf[r]);
+      constexpr int SH = HI16 && (r & 1) ? 16 : 0;
+      if constexpr (kFused) acc_field<W, N, W, P, 0, (1u << W), T, SH>(acc[r], d, cf[r]);
+      else rot_acc<W, N, 0, T, SH>(acc[r], d, cf[r]);
     });
   }
 }
@@ -513,22 +527,35 @@ __device__ __forceinline__ void wait_vmcnt() {
 // One column chunk (64 lanes x 4 bytes) of a wide pass, coded by the G
 // waves of a workgroup: wave g accumulates its MO outputs from every input
 // block, and the blocks reach the waves through a ring of D stages in LDS
-// (`stage`: D x W x 64 dwords) that the waves fill together, each block
-// loaded from HBM once.  Slice t of block j is loaded by wave t mod G
-// straight into stage j mod D (buffer loads to LDS, no registers held).
-// Block j is awaited at step j: each wave waits until its own loads of
-// block j have completed (its later loads, (D - 2) blocks' worth, may still
-// be in flight), then a barrier makes every wave's part visible; stage
+// (`stage`: D x W x 64 dwords, then a 64-dword sink) that the waves fill
+// together, each block loaded from HBM once.  Slice t of block j is loaded
+// by wave t mod G straight into stage j mod D (buffer loads to LDS, no
+// registers held).  Every wave issues NG = ceil(W / G) loads per block:
+// those past slice W - 1 load nothing (an empty descriptor) into the sink,
+// so each wave has the same known count of loads per block in flight.
+// Block j is awaited at step j: each wave waits until its loads of block j
+// have completed (the (D - 2) blocks it issued since may still be in
+// flight), then a barrier makes every wave's part visible; stage
 // (j - 1) mod D, read by every wave before that barrier, is then refilled
 // with block j + D - 1.  Loads past the last block use an empty descriptor
-// (no traffic), so every step issues the same number of loads and the
-// counts awaited are constants.  Lanes past the end of the slice load
-// nothing and store nothing.
-template <int W, int N, uint32_t P, int MO, bool PT, int D, class Src>
+// (no traffic).  Lanes past the end of the slice load nothing and store
+// nothing.
+//
+// Src supplies k(), S(), pitch(), nout(), out(r), in_words() (the k input
+// block addresses, wave-uniform, readable past k: those reads only address
+// loads with an empty descriptor), records() (this wave's coefficient
+// records, one 16-byte record per input block, readable one past the last),
+// unpack(record) -> Lift8 and kHi16 (see accumulate).
+// The per-block scalar work is kept small (running pointers, per-wave
+// constants hoisted): the coefficient dispatch already costs the scalar
+// unit about as many instructions as the XORs cost the vector unit.
+template <int W, int N, uint32_t P, int MO, bool PT, int D, int NG, class Src>
 __device__ __forceinline__ void code_column_staged(const Src &src, uint32_t col, uint32_t lane,
                                                    uint32_t g, uint32_t G, uint32_t *stage) {
-  static_assert((D - 2) * W < 64, "awaited loads must fit vmcnt");
+  static_assert((D - 2) * NG < 64, "awaited loads must fit vmcnt");
+  static_assert((D & (D - 1)) == 0, "stages: a power of two");
   typedef uint32_t T;
+  typedef __attribute__((address_space(3))) void *lds_ptr;
   const int k = src.k();
   const uint32_t S = src.S();
   const uint32_t pitch = src.pitch();
@@ -540,39 +567,49 @@ __device__ __forceinline__ void code_column_staged(const Src &src, uint32_t col,
 #pragma unroll
     for (int i = 0; i < N; ++i) acc[r][i] = 0u;
 
+  // this wave's NG loads per block: slice t_u = g + u G; past slice W - 1 a
+  // slot loads slice t_u mod W again (a duplicate of another wave's load,
+  // served from cache) into the sink after the stages, so that every slot
+  // loads a real slice and no slot needs a per-block test
+  uint32_t soff[NG], loff[NG];
+  static_for<0, NG>([&](auto uc) {
+    constexpr int u = decltype(uc)::value;
+    const uint32_t t = g + (uint32_t)u * G;
+    const bool live = t < (uint32_t)W;
+    soff[u] = (live ? t : t % (uint32_t)W) * pitch;
+    loff[u] = live ? t * 64u : (uint32_t)(D * W * 64);
+  });
+  const auto *ip = src.in_words();     // address of input block jj at ip[jj]
+  const auto *rec = src.records();     // coefficient record of block j at rec[j]
+  constexpr uint32_t kStage = W * 64u;
   auto issue = [&](int jj) {
-    const bool ok = jj < k;
-    const __amdgpu_buffer_rsrc_t r = block_rsrc(src.in(ok ? jj : 0), ok ? span : 0u);
-    uint32_t *base = stage + (uint32_t)(jj % D) * (W * 64u);
-    for (uint32_t t = g; t < (uint32_t)W; t += G)
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(
-          r, (__attribute__((address_space(3))) void *)(base + t * 64u), 4, voff, t * pitch, 0, 0);
-  };
-  // slices this wave loads per block
-  const uint32_t n_g = g < (uint32_t)W ? ((uint32_t)W - g + G - 1) / G : 0u;
-  auto wait_block = [&]() {
-    static_for<1, W + 1>([&](auto c) {
-      constexpr int kC = decltype(c)::value;
-      if (n_g == (uint32_t)kC) wait_vmcnt<(D - 2) * kC>();
+    const uint32_t bytes = jj < k ? span : 0u;
+    const uint8_t *in = (const uint8_t *)ip[jj];
+    const uint32_t slot = (uint32_t)(jj & (D - 1)) * kStage;
+    static_for<0, NG>([&](auto uc) {
+      constexpr int u = decltype(uc)::value;
+      const __amdgpu_buffer_rsrc_t r = block_rsrc(in, bytes);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr)(stage + (slot + loff[u])), 4, voff,
+                                               soff[u], 0, 0);
     });
   };
   for (int jj = 0; jj < D - 1; ++jj) issue(jj);
-  Lift8 cf = src.lift8(0);
+  Lift8 cf = src.unpack(rec[0]);
   for (int j = 0; j < k; ++j) {
-    wait_block();
+    wait_vmcnt<(D - 2) * NG>();
     // (the empty asm statements keep the compiler from moving LDS reads
     // across the barrier, which it does not see as a memory operation)
     __asm__ volatile("" ::: "memory");
     __builtin_amdgcn_s_barrier();
     __asm__ volatile("" ::: "memory");
     issue(j + D - 1);
-    const Lift8 cn = src.lift8(j + 1 < k ? j + 1 : j);
-    const uint32_t *blk = stage + (uint32_t)(j % D) * (W * 64u) + lane;
+    const auto next = rec[j + 1];  // (one record past this group's last: padding)
+    const uint32_t *blk = stage + (uint32_t)(j & (D - 1)) * kStage + lane;
     T d[W];
 #pragma unroll
     for (int t = 0; t < W; ++t) d[t] = blk[t * 64];
-    accumulate<W, N, P, MO, PT, T>(acc, d, cf);
-    cf = cn;
+    accumulate<W, N, P, MO, PT, T, Src::kHi16>(acc, d, cf);
+    cf = src.unpack(next);
   }
   if (col >= S) return;
 #pragma unroll

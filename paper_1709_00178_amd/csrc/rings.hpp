@@ -115,13 +115,24 @@ struct WideArgs {
   uint64_t w[kWideWords];
 };
 constexpr int wide_header_words() { return 3; }
+// Outputs per wave (output group) of a wide launch.  The embedding transform
+// on the ring (6,9) keeps all nine ring slices of an output until the
+// reduction: six outputs per wave (54 accumulators) leave room for seven
+// waves per SIMD, where eight outputs (72) allowed five.  The parity
+// transform drops the high slices, so its outputs cost six accumulators
+// each and keep eight per wave.
+constexpr int wide_max_out(int ring) {
+  return (kRings[ring].n == 9 && !kRings[ring].parity) ? 6 : ring_max_out(ring);
+}
 // Blocks staged in LDS per workgroup of a wide pass (D stages of w slices x
-// 256 bytes: 8 KiB to 15 KiB).
-constexpr int wide_stages(int ring) { return kRings[ring].w <= 6 ? 8 : 6; }
+// 256 bytes, D a power of two: 8 KiB to 12 KiB).
+constexpr int wide_stages(int ring) { return kRings[ring].w <= 6 ? 8 : 4; }
 // Output groups that fit one launch of a k-input code on `ring`.
 constexpr int wide_groups_fit(int ring, int k) {
-  const int per_group = ring_max_out(ring) + 2 * k;  // pointer words + record words
-  const int g = (kWideWords - wide_header_words() - k) / per_group;
+  const int per_group = wide_max_out(ring) + 2 * k;  // pointer words + record words
+  // (two words stay free after the last record: the kernel reads one record
+  // past each group's last)
+  const int g = (kWideWords - 2 - wide_header_words() - k) / per_group;
   return g < kWideMaxGroups ? g : kWideMaxGroups;
 }
 
