@@ -100,14 +100,15 @@ static int run_passes(const pyrit_plan *pl, const uint8_t *const *in, uint8_t *c
 }
 
 // The same outputs in wide launches: each launch codes 2 to
-// wide_groups_fit groups of up to ring_max_out outputs with one read of the
-// inputs (all arguments in the kernel-argument segment).  The outputs of a
-// launch are spread over its groups as evenly as possible; a last group
-// alone takes a plain pass.
+// wide_groups_fit groups of up to wide_max_out outputs with one read of the
+// inputs (all arguments in the kernel-argument segment, laid out as rings.hpp
+// describes).  The outputs of a launch are spread over its groups as evenly
+// as possible; a last pass's worth of outputs alone takes a plain pass.
 static int run_wide(const pyrit_plan *pl, const uint8_t *const *in, uint8_t *const *out, int nout,
                     const uint32_t *coef, size_t S, size_t pitch, void *stream) {
   const int k = pl->k, ring = pl->ring;
   const int MO = wide_max_out(ring);
+  const int RW = wide_rec_words(ring);
   const int fit = wide_groups_fit(ring, k);
   const bool words16 = kRings[ring].n <= 16;
   const uint32_t H = wide_header_words();
@@ -133,13 +134,13 @@ static int run_wide(const pyrit_plan *pl, const uint8_t *const *in, uint8_t *con
     for (int j = 0; j < k; ++j) a.w[H + j] = (uint64_t)(uintptr_t)in[j];
     for (int g = 0; g < G; ++g) {
       const int first = cnt * g / G, n_g = cnt * (g + 1) / G - first;  // 1..MO outputs
-      a.w[2] |= (uint64_t)n_g << (4 * g);
+      a.w[2 + g / 16] |= (uint64_t)n_g << (4 * (g % 16));
       for (int r = 0; r < n_g; ++r) {
         const int o = r0 + first + r;
         a.w[H + k + g * MO + r] = (uint64_t)(uintptr_t)out[o];
         for (int j = 0; j < k; ++j) {
           const uint32_t cw = coef[(size_t)o * k + j];
-          uint8_t *rec = (uint8_t *)&a.w[rec0 + 2 * (g * k + j)];
+          uint8_t *rec = (uint8_t *)&a.w[rec0 + RW * (g * k + j)];
           if (words16) {
             const uint16_t v = (uint16_t)cw;
             std::memcpy(rec + 2 * r, &v, 2);

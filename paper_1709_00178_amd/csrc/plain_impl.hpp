@@ -33,41 +33,45 @@ struct WideSrc {
   __device__ uint32_t S() const { return (uint32_t)(a.w[0] >> 32); }
   __device__ uint32_t pitch() const { return (uint32_t)a.w[1]; }
   __device__ uint32_t groups() const { return (uint32_t)(a.w[1] >> 32); }
-  __device__ int nout() const { return (int)((a.w[2] >> (4 * g)) & 15u); }
+  __device__ int nout() const { return (int)((a.w[2 + g / 16] >> (4 * (g % 16))) & 15u); }
   // the input addresses (read up to k + D - 2 words on: output pointers and
   // records, all inside the argument block)
   __device__ const PYRIT_AS4 uint64_t *in_words() const {
     return (const PYRIT_AS4 uint64_t *)&a.w[kH];
   }
-  template <int MO>
-  __device__ uint8_t *out_of(int r) const {
-    return (uint8_t *)a.w[kH + k() + g * MO + r];
-  }
-  template <int MO>
-  __device__ const PYRIT_AS4 dev::u32x4 *records_of() const {
-    return (const PYRIT_AS4 dev::u32x4 *)&a.w[kH + k() + groups() * MO + 2 * g * (uint32_t)k()];
-  }
 };
-template <int MO, bool WORDS16>
+// Records of RW words: RW = 1 holds up to four 16-bit coefficient words (or
+// two 32-bit ones), RW = 2 up to eight (four).
+template <int MO, int RW, bool WORDS16>
 struct WideGroupSrc : WideSrc {
+  typedef typename dev::Vec<2 * RW>::T Rec;
   // 16-bit words: odd rows read their coefficient from the high half of the
   // 32-bit word in place (accumulate's HI16)
   static constexpr bool kHi16 = WORDS16;
-  __device__ uint8_t *out(int r) const { return out_of<MO>(r); }
-  __device__ const PYRIT_AS4 dev::u32x4 *records() const { return records_of<MO>(); }
-  __device__ dev::Lift8 unpack(dev::u32x4 x) const {
-    if constexpr (WORDS16) {
-      return dev::Lift8{dev::u32x4{x.x & 0xFFFFu, x.x, x.y & 0xFFFFu, x.y},
-                        dev::u32x4{x.z & 0xFFFFu, x.z, x.w & 0xFFFFu, x.w}};
+  __device__ uint8_t *out(int r) const { return (uint8_t *)a.w[kH + k() + g * MO + r]; }
+  __device__ const PYRIT_AS4 Rec *records() const {
+    return (const PYRIT_AS4 Rec *)&a.w[kH + k() + groups() * MO + RW * g * (uint32_t)k()];
+  }
+  __device__ dev::Lift8 unpack(Rec x) const {
+    if constexpr (RW == 1) {
+      if constexpr (WORDS16)
+        return dev::Lift8{dev::u32x4{x.x & 0xFFFFu, x.x, x.y & 0xFFFFu, x.y},
+                          dev::u32x4{0u, 0u, 0u, 0u}};
+      else
+        return dev::Lift8{dev::u32x4{x.x, x.y, 0u, 0u}, dev::u32x4{0u, 0u, 0u, 0u}};
     } else {
-      return dev::Lift8{x, dev::u32x4{0u, 0u, 0u, 0u}};
+      if constexpr (WORDS16)
+        return dev::Lift8{dev::u32x4{x.x & 0xFFFFu, x.x, x.y & 0xFFFFu, x.y},
+                          dev::u32x4{x.z & 0xFFFFu, x.z, x.w & 0xFFFFu, x.w}};
+      else
+        return dev::Lift8{x, dev::u32x4{0u, 0u, 0u, 0u}};
     }
   }
 };
 
-// NG = ceil(w / G): the slices each wave loads per block.  The embedding
-// transform on the ring (6,9) asks for eight waves per SIMD (at most 64
-// VGPRs), which its six outputs per wave fit.
+// NG: the dword loads each wave issues per block.  The embedding transform
+// on the ring (6,9) asks for eight waves per SIMD (at most 64 VGPRs), which
+// its six outputs per wave fit.
 template <int RING>
 constexpr int wide_min_waves() {
   return (kRings[RING].n == 9 && !kRings[RING].parity) ? 8 : 1;
@@ -78,23 +82,28 @@ __attribute__((amdgpu_waves_per_eu(wide_min_waves<RING>()))) void wide_pass_kern
   constexpr RingDesc R = kRings[RING];
   constexpr int MO = wide_max_out(RING);
   constexpr int D = wide_stages(RING);
-  __shared__ uint32_t stage[(D * R.w + 1) * 64];
+  constexpr int V = kWideV;
+  __shared__ uint32_t stage[(D * R.w * V + 1) * 64];
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t G = blockDim.x >> 6;
-  const WideGroupSrc<MO, (R.n <= 16)> src{{a, g}};
-  const uint32_t col = lane_col(plain_chunk_base(blockIdx.x, 1), lane, 1);
-  dev::code_column_staged<R.w, R.n, R.p, MO, R.parity, D, NG>(src, col, lane, g, G, stage);
+  const WideGroupSrc<MO, wide_rec_words(RING), (R.n <= 16)> src{{a, g}};
+  const uint32_t col = lane_col(plain_chunk_base(blockIdx.x, V), lane, V);
+  dev::code_column_staged<R.w, R.n, R.p, MO, R.parity, D, NG, V>(src, col, lane, g, G, stage);
 }
 
+// NG: the power of two at or above ceil(2 w / G) (slots past the block's
+// loads repeat loads into the sink).
 template <int RING, int NG>
 static int launch_wide_ng(int groups, const WideArgs &a, hipStream_t st) {
-  if constexpr (NG > (kRings[RING].w + 1) / 2) {
+  constexpr int kLoads = kRings[RING].w * kWideV;  // dword loads per block
+  if constexpr (NG > 2 * ((kLoads + 1) / 2)) {
     return PYRIT_EINVAL;
   } else {
-    if ((kRings[RING].w + groups - 1) / groups != NG) return launch_wide_ng<RING, NG + 1>(groups, a, st);
+    if (NG * groups < kLoads) return launch_wide_ng<RING, 2 * NG>(groups, a, st);
     const uint32_t S = (uint32_t)(a.w[0] >> 32);
-    const uint32_t blocks = (S + 255u) / 256u;
+    const uint32_t chunk = 256u * kWideV;
+    const uint32_t blocks = (S + chunk - 1) / chunk;
     hipLaunchKernelGGL((wide_pass_kernel<RING, NG>), dim3(blocks), dim3(64 * groups), 0, st, a);
     return hipGetLastError() == hipSuccess ? PYRIT_OK : PYRIT_EHIP;
   }

@@ -524,38 +524,41 @@ __device__ __forceinline__ void wait_vmcnt() {
   __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
-// One column chunk (64 lanes x 4 bytes) of a wide pass, coded by the G
+// One column chunk (64 lanes x 4V bytes) of a wide pass, coded by the G
 // waves of a workgroup: wave g accumulates its MO outputs from every input
 // block, and the blocks reach the waves through a ring of D stages in LDS
-// (`stage`: D x W x 64 dwords, then a 64-dword sink) that the waves fill
-// together, each block loaded from HBM once.  Slice t of block j is loaded
-// by wave t mod G straight into stage j mod D (buffer loads to LDS, no
-// registers held).  Every wave issues NG = ceil(W / G) loads per block:
-// those past slice W - 1 load nothing (an empty descriptor) into the sink,
-// so each wave has the same known count of loads per block in flight.
-// Block j is awaited at step j: each wave waits until its loads of block j
-// have completed (the (D - 2) blocks it issued since may still be in
-// flight), then a barrier makes every wave's part visible; stage
-// (j - 1) mod D, read by every wave before that barrier, is then refilled
-// with block j + D - 1.  Loads past the last block use an empty descriptor
-// (no traffic).  Lanes past the end of the slice load nothing and store
-// nothing.
+// (`stage`: D x W x V x 64 dwords, then a 64-dword sink) that the waves
+// fill together, each block loaded from HBM once.  A block is W V dword
+// loads (load q: dword q mod V of every lane of slice q / V, straight into
+// LDS with buffer loads to LDS, no registers held); wave g issues loads g,
+// g + G, ..., NG = ceil(W V / G) of them per block, a slot past the last
+// load repeating load (its index mod W V) into the sink, so that every wave
+// has the same known count of loads per block in flight and no slot needs a
+// per-block test.  Block j is awaited at step j: each wave waits until its
+// loads of block j have completed (the (D - 2) blocks it issued since may
+// still be in flight), then a barrier makes every wave's part visible;
+// stage (j - 1) mod D, read by every wave before that barrier, is then
+// refilled with block j + D - 1.  Loads past the last block use an empty
+// descriptor (no traffic).  Lanes past the end of the slice load nothing
+// and store nothing.
 //
 // Src supplies k(), S(), pitch(), nout(), out(r), in_words() (the k input
 // block addresses, wave-uniform, readable past k: those reads only address
 // loads with an empty descriptor), records() (this wave's coefficient
-// records, one 16-byte record per input block, readable one past the last),
-// unpack(record) -> Lift8 and kHi16 (see accumulate).
-// The per-block scalar work is kept small (running pointers, per-wave
-// constants hoisted): the coefficient dispatch already costs the scalar
-// unit about as many instructions as the XORs cost the vector unit.
-template <int W, int N, uint32_t P, int MO, bool PT, int D, int NG, class Src>
+// records, one per input block, readable one past the last), unpack(record)
+// -> Lift8 and kHi16 (see accumulate).  The per-block scalar work is kept
+// small (running pointers, per-wave constants hoisted): the coefficient
+// dispatch already costs the scalar unit about as many instructions as the
+// XORs cost the vector unit.
+template <int W, int N, uint32_t P, int MO, bool PT, int D, int NG, int V, class Src>
 __device__ __forceinline__ void code_column_staged(const Src &src, uint32_t col, uint32_t lane,
                                                    uint32_t g, uint32_t G, uint32_t *stage) {
   static_assert((D - 2) * NG < 64, "awaited loads must fit vmcnt");
   static_assert((D & (D - 1)) == 0, "stages: a power of two");
-  typedef uint32_t T;
+  static_assert(V == 1 || V == 2, "lane width");
+  typedef typename Vec<V>::T T;
   typedef __attribute__((address_space(3))) void *lds_ptr;
+  constexpr uint32_t kLoads = W * V;
   const int k = src.k();
   const uint32_t S = src.S();
   const uint32_t pitch = src.pitch();
@@ -565,23 +568,23 @@ __device__ __forceinline__ void code_column_staged(const Src &src, uint32_t col,
 #pragma unroll
   for (int r = 0; r < MO; ++r)
 #pragma unroll
-    for (int i = 0; i < N; ++i) acc[r][i] = 0u;
+    for (int i = 0; i < N; ++i) acc[r][i] = (T)0;
 
-  // this wave's NG loads per block: slice t_u = g + u G; past slice W - 1 a
-  // slot loads slice t_u mod W again (a duplicate of another wave's load,
-  // served from cache) into the sink after the stages, so that every slot
-  // loads a real slice and no slot needs a per-block test
+  // this wave's NG loads per block: load q_u = g + u G (slice q / V, dword
+  // q mod V of each lane), or past the last, load q_u mod W V again into the
+  // sink after the stages
   uint32_t soff[NG], loff[NG];
   static_for<0, NG>([&](auto uc) {
     constexpr int u = decltype(uc)::value;
-    const uint32_t t = g + (uint32_t)u * G;
-    const bool live = t < (uint32_t)W;
-    soff[u] = (live ? t : t % (uint32_t)W) * pitch;
-    loff[u] = live ? t * 64u : (uint32_t)(D * W * 64);
+    const uint32_t q = g + (uint32_t)u * G;
+    const bool live = q < kLoads;
+    const uint32_t qq = live ? q : q % kLoads;
+    soff[u] = (qq / V) * pitch + (qq % V) * 4u;
+    loff[u] = live ? q * 64u : D * kLoads * 64u;
   });
   const auto *ip = src.in_words();     // address of input block jj at ip[jj]
   const auto *rec = src.records();     // coefficient record of block j at rec[j]
-  constexpr uint32_t kStage = W * 64u;
+  constexpr uint32_t kStage = kLoads * 64u;
   auto issue = [&](int jj) {
     const uint32_t bytes = jj < k ? span : 0u;
     const uint8_t *in = (const uint8_t *)ip[jj];
@@ -607,7 +610,12 @@ __device__ __forceinline__ void code_column_staged(const Src &src, uint32_t col,
     const uint32_t *blk = stage + (uint32_t)(j & (D - 1)) * kStage + lane;
     T d[W];
 #pragma unroll
-    for (int t = 0; t < W; ++t) d[t] = blk[t * 64];
+    for (int t = 0; t < W; ++t) {
+      if constexpr (V == 1)
+        d[t] = blk[t * 64];
+      else
+        d[t] = T{blk[(2 * t) * 64], blk[(2 * t + 1) * 64]};
+    }
     accumulate<W, N, P, MO, PT, T, Src::kHi16>(acc, d, cf);
     cf = src.unpack(next);
   }
@@ -618,7 +626,7 @@ __device__ __forceinline__ void code_column_staged(const Src &src, uint32_t col,
     leave_ring<W, N, P, PT, T>(acc[r]);
     const __amdgpu_buffer_rsrc_t o = block_rsrc(src.out(r), span);
 #pragma unroll
-    for (int t = 0; t < W; ++t) bstore<1>(acc[r][t], o, col, t * pitch);
+    for (int t = 0; t < W; ++t) bstore<V>(acc[r][t], o, col, t * pitch);
   }
 }
 

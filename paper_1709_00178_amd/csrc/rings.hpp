@@ -97,39 +97,48 @@ struct PassArgs {
 namespace pyrit {
 
 // ---- wide passes: codes with more outputs than one pass holds ----------
-// One launch codes G output groups of up to ring_max_out outputs each; the G
-// waves of a workgroup share one column chunk, wave g coding group g, and
-// each input block is fetched from HBM once per launch into LDS, where every
-// wave reads it.  Everything travels in the kernel-argument segment, packed
-// into kWideWords 8-byte words:
+// One launch codes G output groups of up to wide_max_out outputs each; the
+// G waves of a workgroup share one column chunk of 64 lanes x 4 bytes,
+// wave g coding group g, and each input block is fetched from HBM once per
+// launch into LDS, where every wave reads it.  Everything travels in the
+// kernel-argument segment, packed into kWideWords 8-byte words:
 //   word 0: k | S << 32;  word 1: pitch | groups << 32;
-//   word 2: the number of outputs of group g (1..8) in bits 4g..4g+3;
-//   words 3..3+k: input pointers;
-//   then G x ring_max_out output pointers (group g's at g * ring_max_out);
-//   then G x k records of 16 bytes, (g, j) at (g * k + j): the coefficient
-//   words of input j for group g's outputs, as 16-bit words (n <= 16, up to
-//   eight outputs) or 32-bit words (n = 17, four outputs).
+//   words 2, 3: the number of outputs of group g (1..15) in bits 4g..4g+3
+//     of the 128-bit value word 2 | word 3 << 64;
+//   words 4..4+k: input pointers;
+//   then G x wide_max_out output pointers (group g's at g * wide_max_out);
+//   then G x k records of wide_rec_words words, (g, j) at (g * k + j): the
+//   coefficient words of input j for group g's outputs, as 16-bit words
+//   (n <= 16) or 32-bit words (n = 17).
 constexpr int kWideWords = 500;         // 4000 bytes of kernel arguments
-constexpr int kWideMaxGroups = 8;       // waves per workgroup
+constexpr int kWideMaxGroups = 16;      // waves per workgroup
+constexpr int kWideV = 1;               // dwords per lane
 struct WideArgs {
   uint64_t w[kWideWords];
 };
-constexpr int wide_header_words() { return 3; }
-// Outputs per wave (output group) of a wide launch.  The embedding transform
-// on the ring (6,9) keeps all nine ring slices of an output until the
-// reduction: six outputs per wave (54 accumulators) leave room for seven
-// waves per SIMD, where eight outputs (72) allowed five.  The parity
-// transform drops the high slices, so its outputs cost six accumulators
-// each and keep eight per wave.
+constexpr int wide_header_words() { return 4; }
+// Outputs per wave (output group) of a wide launch, with lanes of 4 bytes.
+// The embedding transform on the ring (6,9) keeps all nine ring slices of
+// an output until the reduction: six outputs per wave (54 accumulators)
+// fit eight waves per SIMD, where eight outputs (72) allowed five, and ran
+// the (60,40) and (60,20) codes 15-25% faster.  The parity transform drops
+// the high slices (six accumulators per output) and keeps eight.  (8-byte
+// lanes, which halve the scalar dispatch work per byte, measured no faster:
+// their accumulators left five to seven waves per SIMD.)
 constexpr int wide_max_out(int ring) {
   return (kRings[ring].n == 9 && !kRings[ring].parity) ? 6 : ring_max_out(ring);
+}
+// Record words per (group, input): 16-bit coefficient words, four per word
+// (n <= 16), or 32-bit ones, two per word (n = 17).
+constexpr int wide_rec_words(int ring) {
+  return kRings[ring].n <= 16 ? (wide_max_out(ring) + 3) / 4 : (wide_max_out(ring) + 1) / 2;
 }
 // Blocks staged in LDS per workgroup of a wide pass (D stages of w slices x
 // 256 bytes, D a power of two: 8 KiB to 12 KiB).
 constexpr int wide_stages(int ring) { return kRings[ring].w <= 6 ? 8 : 4; }
 // Output groups that fit one launch of a k-input code on `ring`.
 constexpr int wide_groups_fit(int ring, int k) {
-  const int per_group = wide_max_out(ring) + 2 * k;  // pointer words + record words
+  const int per_group = wide_max_out(ring) + wide_rec_words(ring) * k;
   // (two words stay free after the last record: the kernel reads one record
   // past each group's last)
   const int g = (kWideWords - 2 - wide_header_words() - k) / per_group;
