@@ -192,7 +192,35 @@ def cpu_baseline(target_s: float = 10.0):
             "sample": f"GF(2^8) k=10 m=4 Cauchy encode of a {Sp >> 20} MiB column sample of every "
                       f"slice ({st.k * st.w * Sp / 1e6:.0f} MB of data) x {reps} passes, {el:.1f} s",
             "single_thread_GBps": round(st.k * st.w * S1 * reps1 / el1 / 1e9, 4),
+            "other_codes": cpu_other_codes(nt, target_s / 4),
             "host_cpu": host_cpu()}
+
+
+def cpu_other_codes(nt, target_s):
+    """The oracle on the GF(2^4) k=4 m=2 code (its whole 64 KiB-block stripe)
+    and the GF(2^10) k=16 m=4 code (a 256 KiB column sample of every slice of
+    one stripe), all host threads: data GB/s of each."""
+    import numpy as np
+
+    import oracle
+    from paper_1709_00178_amd import workloads as W
+    res = {}
+    for name, st, S in (("gf16_k4_m2", W.c0(), None), ("gf1024_k16_m4", W.c2(1)[0], 256 << 10)):
+        S = S or st.S
+        f = oracle.Field(st.w, st.p)
+        C = f.cauchy(st.k, st.m)
+        data = [W.block_bytes(st.key(j), st.w * S) for j in range(st.k)]
+        par = [np.zeros(st.w * S, dtype=np.uint8) for _ in range(st.m)]
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            f.encode(C, data, S, nthreads=nt, parity=par)
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= target_s or reps >= 4096:
+                break
+        res[name] = {"GBps_data": round(st.k * st.w * S * reps / el / 1e9, 4),
+                     "sample_bytes": st.k * st.w * S, "passes": reps}
+    return res
 
 
 # Executor of the C1 batch: grid mode, 256-thread workgroups of two split-K
