@@ -573,7 +573,10 @@ __device__ __forceinline__ void code_column_staged(const Src &src, uint32_t col,
   // this wave's NG loads per block: load q_u = g + u G (slice q / V, dword
   // q mod V of each lane), or past the last, load q_u mod W V again into the
   // sink after the stages
-  uint32_t soff[NG], loff[NG];
+  // (the LDS target of load u for the block in stage `slot` is
+  // (slot & smask[u]) + loff[u]: the stage row of a live load, the sink for
+  // any block otherwise)
+  uint32_t soff[NG], loff[NG], smask[NG];
   static_for<0, NG>([&](auto uc) {
     constexpr int u = decltype(uc)::value;
     const uint32_t q = g + (uint32_t)u * G;
@@ -581,6 +584,7 @@ __device__ __forceinline__ void code_column_staged(const Src &src, uint32_t col,
     const uint32_t qq = live ? q : q % kLoads;
     soff[u] = (qq / V) * pitch + (qq % V) * 4u;
     loff[u] = live ? q * 64u : D * kLoads * 64u;
+    smask[u] = live ? 0xFFFFFFFFu : 0u;
   });
   const auto *ip = src.in_words();     // address of input block jj at ip[jj]
   const auto *rec = src.records();     // coefficient record of block j at rec[j]
@@ -592,8 +596,8 @@ __device__ __forceinline__ void code_column_staged(const Src &src, uint32_t col,
     static_for<0, NG>([&](auto uc) {
       constexpr int u = decltype(uc)::value;
       const __amdgpu_buffer_rsrc_t r = block_rsrc(in, bytes);
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr)(stage + (slot + loff[u])), 4, voff,
-                                               soff[u], 0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr)(stage + ((slot & smask[u]) + loff[u])),
+                                               4, voff, soff[u], 0, 0);
     });
   };
   for (int jj = 0; jj < D - 1; ++jj) issue(jj);

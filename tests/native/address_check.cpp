@@ -1,7 +1,8 @@
 // Address model of every load and store the coding kernels issue, checked on
-// the host: the plain kernel (every lane width) and the batch kernel's
-// executors (grid with and without split-K pairs and XCD order, queue,
-// static), on seeded mixed batches with ragged and padded slices.  The work
+// the host: the plain kernel (every lane width), the wide kernel (every ring
+// and group count) and the batch kernel's executors (grid with and without
+// split-K pairs and XCD order, queue, static), on seeded mixed batches with
+// ragged and padded slices.  The work
 // comes from the real batch builder (build_batch_image) and the column of
 // every lane from the formulas the kernels use (rings.hpp, batch_abi.hpp).
 //
@@ -160,6 +161,48 @@ void walk_plain(uint32_t w, uint32_t S, uint32_t pitch, uint32_t V, uint32_t k) 
   for (uint32_t b = 0; b < blocks; ++b) wave_chunk(w, S, pitch, V, k, plain_chunk_base(b, V));
 }
 
+// The wide kernel (plain_impl.hpp, ring_kernels.hpp code_column_staged):
+// workgroup b = G waves on the chunk of 64 lanes x 4 kWideV bytes at
+// plain_chunk_base(b, kWideV); each wave issues NG dword loads per block,
+// load q = g + u G (q < w kWideV: dword q mod kWideV of every lane of slice
+// q / kWideV; past that, load q mod w kWideV again into the sink), each
+// lane loading 4 bytes at voffset lane_load_voffset(col, S) plus soffset.
+// Besides the global addresses, every LDS target must lie in the stage ring
+// plus sink of D w kWideV + 1 rows of 64 dwords.
+void walk_wide(uint32_t w, uint32_t S, uint32_t pitch, uint32_t k, uint32_t D) {
+  const uint32_t V = (uint32_t)kWideV, kLoads = w * V;
+  const uint32_t span = block_span(w, S, pitch);
+  const uint32_t chunk = 64u * 4u * V;
+  const uint32_t blocks = (S + chunk - 1) / chunk;
+  for (uint32_t G = 2; G <= (uint32_t)kWideMaxGroups; ++G) {
+    uint32_t NG = 1;
+    while (NG * G < kLoads) NG *= 2;
+    for (uint32_t b = 0; b < blocks; ++b)
+      for (uint32_t g = 0; g < G; ++g)
+        for (uint32_t lane = 0; lane < 64; ++lane) {
+          const uint32_t col = lane_col(plain_chunk_base(b, V), lane, V);
+          const uint32_t voff = old_rule ? col : lane_load_voffset(col, S);
+          for (uint32_t u = 0; u < NG; ++u) {
+            const uint32_t q = g + u * G;
+            const uint32_t qq = q < kLoads ? q : q % kLoads;
+            const uint64_t soff = (uint64_t)(qq / V) * pitch + (qq % V) * 4u;
+            const uint32_t loff = q < kLoads ? q * 64u : D * kLoads * 64u;
+            const uint32_t smask = q < kLoads ? 0xFFFFFFFFu : 0u;
+            for (uint32_t jj = 0; jj < k + D - 1; ++jj) {
+              const uint32_t slot = (jj & (D - 1)) * kLoads * 64u;
+              CHECK((slot & smask) + loff + lane < (D * kLoads + 1) * 64u);  // LDS target
+              const uint32_t bytes = jj < k ? span : 0u;
+              const bool in_a = voff < bytes, in_b = (uint64_t)voff + soff < bytes;
+              if (!in_a && !in_b) continue;
+              ++loads;
+              if ((uint64_t)voff + soff + 4u > span) ++violations;
+            }
+          }
+          lane_stores(w, S, pitch, V, col);
+        }
+  }
+}
+
 struct Ring {
   int w, n;
   uint32_t p;
@@ -182,6 +225,14 @@ void run_model() {
         const uint32_t pitch = rnd(2) ? S : S + 64u * rnd(70);
         walk_plain(w, S, pitch, V, 1 + rnd(4));
       }
+  // wide kernel: every ring's slice count and stage depth, ragged and padded
+  for (int ring = 0; ring < kNumRings; ++ring)
+    for (int trial = 0; trial < 6; ++trial) {
+      const uint32_t w = (uint32_t)kRings[ring].w;
+      const uint32_t S = 64u * (1u + rnd(trial < 3 ? 12 : 100));
+      const uint32_t pitch = rnd(2) ? S : S + 64u * rnd(70);
+      walk_wide(w, S, pitch, 1 + rnd(5), (uint32_t)wide_stages(ring));
+    }
   const Ring rings[] = {{4, 5, 0x1F, 0}, {8, 17, 0x139, 0}, {8, 17, 0x1D7, 0}, {10, 11, 0x7FF, 0},
                         {6, 9, 0x49, 0},  {4, 5, 0x1F, 1},   {10, 11, 0x7FF, 1}, {6, 9, 0x49, 1}};
   uint64_t next_addr = 1ull << 36;
