@@ -24,6 +24,10 @@
 namespace pyrit {
 namespace {
 
+// Requests launched as one plain kernel each rather than one batch kernel
+// (see the launch step of pyrit_server_run).
+constexpr int kPlainLaunchMax = 4;
+
 // First-fit allocator over [0, size) with coalescing frees.
 class PoolAlloc {
  public:
@@ -296,17 +300,23 @@ int pyrit_server_run(pyrit_server *sv, const pyrit_request *reqs, int n, pyrit_r
           at += reqs[i].plan->k + reqs[i].plan->m;
         }
         int rc;
-        // A launch of one request runs the plain kernel directly: its
-        // arguments travel in the kernel-argument segment, with no descriptor
-        // upload ahead of it.
-        if (take == 1) {
-          const pyrit_batch_item &it = items[0];
-          if (it.n_erased == 0)
-            rc = pyrit_encode_ex(it.plan, (const uint8_t *const *)it.blocks, it.blocks + it.plan->k,
-                                 it.slice_bytes, it.slice_pitch, 0, sl.stream);
-          else
-            rc = pyrit_decode_ex(it.plan, it.erased, it.n_erased, it.blocks, it.slice_bytes,
-                                 it.slice_pitch, sl.stream);
+        // A launch of up to kPlainLaunchMax requests runs the plain kernel
+        // once per request, back to back on the slot's stream: the arguments
+        // travel in the kernel-argument segment, with no descriptor upload
+        // ahead of them (the upload cost a two-request batch more than a
+        // second plain launch at 20 k req/s).
+        if (take <= kPlainLaunchMax) {
+          rc = PYRIT_OK;
+          for (int q = 0; q < take && rc == PYRIT_OK; ++q) {
+            const pyrit_batch_item &it = items[q];
+            if (it.n_erased == 0)
+              rc = pyrit_encode_ex(it.plan, (const uint8_t *const *)it.blocks,
+                                   it.blocks + it.plan->k, it.slice_bytes, it.slice_pitch, 0,
+                                   sl.stream);
+            else
+              rc = pyrit_decode_ex(it.plan, it.erased, it.n_erased, it.blocks, it.slice_bytes,
+                                   it.slice_pitch, sl.stream);
+          }
         } else {
           rc = build_batch_image(items.data(), (int)items.size(), cfg.tune, sv->resident_grid,
                                  (uint64_t)(uintptr_t)sl.dbuf, &bi);

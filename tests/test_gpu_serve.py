@@ -116,6 +116,30 @@ def test_served_mix_equals_alone_and_oracle():
     del torch
 
 
+def test_burst_takes_both_launch_forms():
+    """Bursts of requests on one launch slot: a launch of few requests runs
+    plain kernels back to back, a launch of many one batch kernel.  Every
+    request's outputs equal its outputs coded alone."""
+    # three requests at once, then 40 more at once 20 ms later: the first
+    # launch carries three requests, the later ones twelve
+    trace = small_trace(n=43, rate=1e9, seed=29, large_every=1000)
+    trace = trace[:3] + [dataclasses.replace(r, arrival_s=r.arrival_s + 0.02) for r in trace[3:]]
+    inputs = serve.InputPool(256 << 20, key=0xB0B)
+    plans = {}
+    prep = serve.prepare(trace, inputs, plans)
+    sv = serve.Server(pool_bytes=4 << 30, slots=1, max_batch=12, release_outputs=False)
+    res, stats = sv.run(prep.array)
+    sizes = np.bincount(res["launch"])
+    assert sizes.max() > 4 and sizes.min() <= 4, sizes  # both launch forms ran
+    for i, (st, offs, large) in enumerate(prep.meta):
+        plan = plans[(st.w, st.n, st.p, st.k, st.m)]
+        alone, _ = _alone(plan, st, inputs, offs)
+        for q, blk in enumerate(alone):
+            mixed = _pool_view(sv, int(res[i]["out_offset"] + q * res[i]["out_stride"]), st.block_len)
+            assert np.array_equal(mixed[:st.block_len], blk), (i, q, st)
+    sv.close()
+
+
 def test_served_mix_with_256_byte_aligned_slices():
     """Requests whose slices start at 256-byte boundaries (slice pitch = S
     rounded up to 256, as the benchmark serves them): every coded slice equals
