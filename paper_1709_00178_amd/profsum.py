@@ -1,9 +1,10 @@
 """Summaries of rocprofv3 CSV output for the committed profiles.
 
     python -m paper_1709_00178_amd.profsum stats  <run_kernel_stats.csv>  --cmd "..." \\
-        [--marker NAME --kernel NAME] > out.md
+        [--marker NAME --kernel NAME] [--by-grid TEXT] > out.md
     python -m paper_1709_00178_amd.profsum traffic --fetch <dir> --write <dir> --kernel NAME \\
-        --copy-bytes N --record KEY [--algorithmic BYTES] --cmd "..." > out.md
+        --copy-bytes N --record KEY [--algorithmic BYTES] [--fetch-kib LO:HI] \\
+        [--write-kib LO:HI] [--copy-fetch <dir> --copy-write <dir>] --cmd "..." > out.md
 
 `traffic` turns per-dispatch FETCH_SIZE and WRITE_SIZE (KiB) of a kernel
 into HBM bytes per launch, each scaled by what the same counter reads for the
@@ -64,6 +65,24 @@ def stats_table(path: str) -> str:
     return "\n".join(out)
 
 
+def grid_table(stats_path: str, needle: str) -> str:
+    """Dispatch durations per (kernel, grid size) for the kernels whose name
+    holds `needle`, from the kernel trace beside the stats file: one row per
+    launch shape, so calls of one kernel on different block sizes stay apart."""
+    tpath = stats_path.replace("kernel_stats.csv", "kernel_trace.csv")
+    d: dict = {}
+    for r in csv.DictReader(open(tpath)):
+        if needle in r["Kernel_Name"]:
+            key = (r["Kernel_Name"], int(r["Grid_Size_X"]), int(r["Workgroup_Size_X"]))
+            d.setdefault(key, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    out = ["| kernel | grid (threads) | workgroup | calls | mean us | median us | min us | max us |",
+           "|---|---:|---:|---:|---:|---:|---:|---:|"]
+    for (name, grid, wg), v in sorted(d.items()):
+        out.append(f"| `{name}` | {grid} | {wg} | {len(v)} | {statistics.fmean(v):.1f} | "
+                   f"{statistics.median(v):.1f} | {min(v):.1f} | {max(v):.1f} |")
+    return "\n".join(out)
+
+
 def marked_launches(stats_path: str, marker: str, kernel: str):
     """Durations (us) of the dispatches of `kernel` that ran wholly inside
     the marker range `marker` (rocprofv3 --marker-trace beside the stats)."""
@@ -82,13 +101,21 @@ def marked_launches(stats_path: str, marker: str, kernel: str):
     return out
 
 
-def counter_means(directory: str, counter: str) -> dict:
-    """Mean value of `counter` per kernel name over its dispatches."""
+def kib_range(text: str):
+    """'LO:HI' in KiB (either side may be empty) -> (lo, hi)."""
+    lo, _, hi = text.partition(":")
+    return float(lo or 0.0), float(hi or "inf")
+
+
+def counter_means(directory: str, counter: str, kib=(0.0, float("inf"))) -> dict:
+    """Mean value of `counter` per kernel name over its dispatches, keeping
+    only dispatches whose value lies in the KiB range `kib` (the launches of
+    one workload when the same kernel codes other shapes in the run)."""
     files = glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)
     vals: dict = {}
     for fn in files:
         for r in csv.DictReader(open(fn)):
-            if r["Counter_Name"] == counter:
+            if r["Counter_Name"] == counter and kib[0] <= float(r["Counter_Value"]) <= kib[1]:
                 vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
     return {k: (statistics.fmean(v), len(v)) for k, v in vals.items()}
 
@@ -108,12 +135,21 @@ def main():
     a.add_argument("--cmd", required=True)
     a.add_argument("--marker", default="")
     a.add_argument("--kernel", default="")
+    a.add_argument("--by-grid", default="", help="also tabulate, per grid size, the kernels "
+                   "whose name holds this text")
     b = sub.add_parser("traffic")
     b.add_argument("--fetch", required=True)
     b.add_argument("--write", required=True)
     b.add_argument("--kernel", required=True)
     b.add_argument("--copy-kernel", default="copy_kernel")
     b.add_argument("--copy-bytes", type=int, required=True)
+    b.add_argument("--copy-fetch", default="", help="FETCH_SIZE run holding the copy kernel "
+                   "(default: the --fetch run)")
+    b.add_argument("--copy-write", default="", help="WRITE_SIZE run holding the copy kernel "
+                   "(default: the --write run)")
+    b.add_argument("--fetch-kib", default=":", help="LO:HI, keep dispatches whose FETCH_SIZE "
+                   "(KiB) lies in the range")
+    b.add_argument("--write-kib", default=":", help="LO:HI, the same for WRITE_SIZE")
     b.add_argument("--record", required=True)
     b.add_argument("--algorithmic", type=int, default=0)
     b.add_argument("--cmd", required=True)
@@ -121,6 +157,9 @@ def main():
     if args.what == "stats":
         print(f"Command: `{args.cmd}`\n")
         print(stats_table(args.csv))
+        if args.by_grid:
+            print("\nPer launch shape:\n")
+            print(grid_table(args.csv, args.by_grid))
         if args.marker:
             d = marked_launches(args.csv, args.marker, args.kernel)
             print(f"\nInside the marker range `{args.marker}` (the bench's timed steps): "
@@ -128,12 +167,12 @@ def main():
                   f"median {statistics.median(d):.1f} us, min {min(d):.1f} us, "
                   f"max {max(d):.1f} us.")
         return
-    fetch = counter_means(args.fetch, "FETCH_SIZE")
-    write = counter_means(args.write, "WRITE_SIZE")
+    fetch = counter_means(args.fetch, "FETCH_SIZE", kib_range(args.fetch_kib))
+    write = counter_means(args.write, "WRITE_SIZE", kib_range(args.write_kib))
     (kf, nf), name = find(fetch, args.kernel)
     (kw, nw), _ = find(write, args.kernel)
-    (cf, _), _ = find(fetch, args.copy_kernel)
-    (cw, _), _ = find(write, args.copy_kernel)
+    (cf, _), _ = find(counter_means(args.copy_fetch or args.fetch, "FETCH_SIZE"), args.copy_kernel)
+    (cw, _), _ = find(counter_means(args.copy_write or args.write, "WRITE_SIZE"), args.copy_kernel)
     half_kib = args.copy_bytes / 2 / 1024
     f_scale, w_scale = half_kib / cf, half_kib / cw
     traffic = int(round((kf * f_scale + kw * w_scale) * 1024))
@@ -148,6 +187,13 @@ def main():
         f.write("\n")
     print(f"Command: `{args.cmd}` (one `--pmc FETCH_SIZE` run, one `--pmc WRITE_SIZE` run)\n")
     print(f"Kernel: `{name}`\n")
+    if args.fetch_kib != ":" or args.write_kib != ":":
+        print(f"Dispatches kept: FETCH_SIZE in [{args.fetch_kib}] KiB and WRITE_SIZE in "
+              f"[{args.write_kib}] KiB (this workload's launches; the same kernel codes other "
+              f"shapes in the run).\n")
+    if args.copy_fetch or args.copy_write:
+        print(f"Copy-kernel calibration from the runs `{args.copy_fetch or args.fetch}` and "
+              f"`{args.copy_write or args.write}` (same counters, same session).\n")
     print("| quantity | value |\n|---|---:|")
     print(f"| FETCH_SIZE per dispatch (KiB, mean of {nf}) | {kf:.1f} |")
     print(f"| WRITE_SIZE per dispatch (KiB, mean of {nw}) | {kw:.1f} |")
