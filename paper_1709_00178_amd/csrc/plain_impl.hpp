@@ -71,7 +71,7 @@ struct WideGroupSrc : WideSrc {
 
 // NG: the dword loads each wave issues per block.  The embedding transform
 // on the ring (6,9) asks for eight waves per SIMD (at most 64 VGPRs), which
-// its six outputs per wave fit.
+// its five outputs per wave fit.
 template <int RING>
 constexpr int wide_min_waves() {
   return (kRings[RING].n == 9 && !kRings[RING].parity) ? 8 : 1;
@@ -89,7 +89,8 @@ __attribute__((amdgpu_waves_per_eu(wide_min_waves<RING>()))) void wide_pass_kern
   const uint32_t G = blockDim.x >> 6;
   const WideGroupSrc<MO, wide_rec_words(RING), (R.n <= 16)> src{{a, g}};
   const uint32_t col = lane_col(plain_chunk_base(blockIdx.x, V), lane, V);
-  dev::code_column_staged<R.w, R.n, R.p, MO, R.parity, D, NG, V>(src, col, lane, g, G, stage);
+  dev::code_column_staged<R.w, R.n, R.p, MO, R.parity, D, wide_blocks_per_barrier(RING), NG, V>(
+      src, col, lane, g, G, stage);
 }
 
 // NG: the power of two at or above ceil(2 w / G) (slots past the block's

@@ -534,26 +534,29 @@ __device__ __forceinline__ void wait_vmcnt() {
 // g + G, ..., NG = ceil(W V / G) of them per block, a slot past the last
 // load repeating load (its index mod W V) into the sink, so that every wave
 // has the same known count of loads per block in flight and no slot needs a
-// per-block test.  Block j is awaited at step j: each wave waits until its
-// loads of block j have completed (the (D - 2) blocks it issued since may
-// still be in flight), then a barrier makes every wave's part visible;
-// stage (j - 1) mod D, read by every wave before that barrier, is then
-// refilled with block j + D - 1.  Loads past the last block use an empty
-// descriptor (no traffic).  Lanes past the end of the slice load nothing
-// and store nothing.
+// per-block test.  The blocks are coded B at a time: at step j (a multiple
+// of B) each wave waits until its loads of blocks j .. j + B - 1 have
+// completed (the D - 2B blocks it issued since may still be in flight), then
+// a barrier makes every wave's part visible; the B stages read by every
+// wave before that barrier are then refilled with blocks j + D - B ..
+// j + D - 1.  Loads past the last block use an empty descriptor (no
+// traffic).  Lanes past the end of the slice load nothing and store
+// nothing.
 //
 // Src supplies k(), S(), pitch(), nout(), out(r), in_words() (the k input
 // block addresses, wave-uniform, readable past k: those reads only address
 // loads with an empty descriptor), records() (this wave's coefficient
-// records, one per input block, readable one past the last), unpack(record)
+// records, one per input block, readable one past the last; at most B - 1
+// blocks past the last are skipped), unpack(record)
 // -> Lift8 and kHi16 (see accumulate).  The per-block scalar work is kept
 // small (running pointers, per-wave constants hoisted): the coefficient
 // dispatch already costs the scalar unit about as many instructions as the
 // XORs cost the vector unit.
-template <int W, int N, uint32_t P, int MO, bool PT, int D, int NG, int V, class Src>
+template <int W, int N, uint32_t P, int MO, bool PT, int D, int B, int NG, int V, class Src>
 __device__ __forceinline__ void code_column_staged(const Src &src, uint32_t col, uint32_t lane,
                                                    uint32_t g, uint32_t G, uint32_t *stage) {
-  static_assert((D - 2) * NG < 64, "awaited loads must fit vmcnt");
+  static_assert((D - 2 * B) * NG < 64, "awaited loads must fit vmcnt");
+  static_assert(B == 1 || B == 2, "blocks per barrier");
   static_assert((D & (D - 1)) == 0, "stages: a power of two");
   static_assert(V == 1 || V == 2, "lane width");
   typedef typename Vec<V>::T T;
@@ -600,28 +603,33 @@ __device__ __forceinline__ void code_column_staged(const Src &src, uint32_t col,
                                                4, voff, soff[u], 0, 0);
     });
   };
-  for (int jj = 0; jj < D - 1; ++jj) issue(jj);
+  for (int jj = 0; jj < D - B; ++jj) issue(jj);
   Lift8 cf = src.unpack(rec[0]);
-  for (int j = 0; j < k; ++j) {
-    wait_vmcnt<(D - 2) * NG>();
+  for (int j = 0; j < k; j += B) {
+    wait_vmcnt<(D - 2 * B) * NG>();
     // (the empty asm statements keep the compiler from moving LDS reads
     // across the barrier, which it does not see as a memory operation)
     __asm__ volatile("" ::: "memory");
     __builtin_amdgcn_s_barrier();
     __asm__ volatile("" ::: "memory");
-    issue(j + D - 1);
-    const auto next = rec[j + 1];  // (one record past this group's last: padding)
-    const uint32_t *blk = stage + (uint32_t)(j & (D - 1)) * kStage + lane;
-    T d[W];
+    static_for<0, B>([&](auto bc) { issue(j + D - B + decltype(bc)::value); });
+    static_for<0, B>([&](auto bc) {
+      constexpr int b = decltype(bc)::value;
+      const int jb = j + b;
+      if (b > 0 && jb >= k) return;
+      const auto next = rec[jb + 1];  // (one record past this group's last: padding)
+      const uint32_t *blk = stage + (uint32_t)(jb & (D - 1)) * kStage + lane;
+      T d[W];
 #pragma unroll
-    for (int t = 0; t < W; ++t) {
-      if constexpr (V == 1)
-        d[t] = blk[t * 64];
-      else
-        d[t] = T{blk[(2 * t) * 64], blk[(2 * t + 1) * 64]};
-    }
-    accumulate<W, N, P, MO, PT, T, Src::kHi16>(acc, d, cf);
-    cf = src.unpack(next);
+      for (int t = 0; t < W; ++t) {
+        if constexpr (V == 1)
+          d[t] = blk[t * 64];
+        else
+          d[t] = T{blk[(2 * t) * 64], blk[(2 * t + 1) * 64]};
+      }
+      accumulate<W, N, P, MO, PT, T, Src::kHi16>(acc, d, cf);
+      cf = src.unpack(next);
+    });
   }
   if (col >= S) return;
 #pragma unroll

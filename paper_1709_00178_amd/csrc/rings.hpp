@@ -118,15 +118,19 @@ struct WideArgs {
 };
 constexpr int wide_header_words() { return 4; }
 // Outputs per wave (output group) of a wide launch, with lanes of 4 bytes.
-// The embedding transform on the ring (6,9) keeps all nine ring slices of
-// an output until the reduction: six outputs per wave (54 accumulators)
-// fit eight waves per SIMD, where eight outputs (72) allowed five, and ran
-// the (60,40) and (60,20) codes 15-25% faster.  The parity transform drops
-// the high slices (six accumulators per output) and keeps eight.  (8-byte
-// lanes, which halve the scalar dispatch work per byte, measured no faster:
-// their accumulators left five to seven waves per SIMD.)
+// On the ring (6,9), five: the embedding transform keeps all nine ring
+// slices of an output until the reduction, and five outputs (45
+// accumulators) fit eight waves per SIMD with no register spill, where six
+// (54) spilled and eight (72) allowed five waves; the parity transform
+// keeps six slices per output.  Groups of five also split the paper's
+// (60,40) and (60,20) shapes (20 and 40 parity blocks) evenly, so no wave
+// dispatches on padding coefficients.  Against six (embedding) and eight
+// (parity) outputs per wave this ran those codes 5-20% faster; four per
+// wave ran 10-25% slower (more waves, each reading every input block from
+// LDS).  8-byte lanes, which halve the scalar dispatch work per byte,
+// measured slower at every group size tried.
 constexpr int wide_max_out(int ring) {
-  return (kRings[ring].n == 9 && !kRings[ring].parity) ? 6 : ring_max_out(ring);
+  return kRings[ring].n == 9 ? 5 : ring_max_out(ring);
 }
 // Record words per (group, input): 16-bit coefficient words, four per word
 // (n <= 16), or 32-bit ones, two per word (n = 17).
@@ -136,6 +140,12 @@ constexpr int wide_rec_words(int ring) {
 // Blocks staged in LDS per workgroup of a wide pass (D stages of w slices x
 // 256 bytes, D a power of two: 8 KiB to 12 KiB).
 constexpr int wide_stages(int ring) { return kRings[ring].w <= 6 ? 8 : 4; }
+// Blocks coded between two barriers of a wide pass: two where eight stages
+// leave room to prefetch six blocks ahead (half the barriers, and waves
+// whose coefficients cost more on one block catch up on the next: 2-9%
+// faster on the (60,40) and (60,20) codes than one block per barrier; four
+// per barrier, or two with sixteen stages, ran slower), else one.
+constexpr int wide_blocks_per_barrier(int ring) { return wide_stages(ring) >= 8 ? 2 : 1; }
 // Output groups that fit one launch of a k-input code on `ring`.
 constexpr int wide_groups_fit(int ring, int k) {
   const int per_group = wide_max_out(ring) + wide_rec_words(ring) * k;

@@ -167,9 +167,11 @@ void walk_plain(uint32_t w, uint32_t S, uint32_t pitch, uint32_t V, uint32_t k) 
 // load q = g + u G (q < w kWideV: dword q mod kWideV of every lane of slice
 // q / kWideV; past that, load q mod w kWideV again into the sink), each
 // lane loading 4 bytes at voffset lane_load_voffset(col, S) plus soffset.
-// Besides the global addresses, every LDS target must lie in the stage ring
-// plus sink of D w kWideV + 1 rows of 64 dwords.
-void walk_wide(uint32_t w, uint32_t S, uint32_t pitch, uint32_t k, uint32_t D) {
+// Blocks are issued B at a time, through block roundup(k, B) + D - B - 1
+// (those at or past k with an empty descriptor).  Besides the global
+// addresses, every LDS target must lie in the stage ring plus sink of
+// D w kWideV + 1 rows of 64 dwords.
+void walk_wide(uint32_t w, uint32_t S, uint32_t pitch, uint32_t k, uint32_t D, uint32_t B) {
   const uint32_t V = (uint32_t)kWideV, kLoads = w * V;
   const uint32_t span = block_span(w, S, pitch);
   const uint32_t chunk = 64u * 4u * V;
@@ -188,7 +190,8 @@ void walk_wide(uint32_t w, uint32_t S, uint32_t pitch, uint32_t k, uint32_t D) {
             const uint64_t soff = (uint64_t)(qq / V) * pitch + (qq % V) * 4u;
             const uint32_t loff = q < kLoads ? q * 64u : D * kLoads * 64u;
             const uint32_t smask = q < kLoads ? 0xFFFFFFFFu : 0u;
-            for (uint32_t jj = 0; jj < k + D - 1; ++jj) {
+            const uint32_t issued = (k + B - 1) / B * B + D - B;
+            for (uint32_t jj = 0; jj < issued; ++jj) {
               const uint32_t slot = (jj & (D - 1)) * kLoads * 64u;
               CHECK((slot & smask) + loff + lane < (D * kLoads + 1) * 64u);  // LDS target
               const uint32_t bytes = jj < k ? span : 0u;
@@ -231,7 +234,8 @@ void run_model() {
       const uint32_t w = (uint32_t)kRings[ring].w;
       const uint32_t S = 64u * (1u + rnd(trial < 3 ? 12 : 100));
       const uint32_t pitch = rnd(2) ? S : S + 64u * rnd(70);
-      walk_wide(w, S, pitch, 1 + rnd(5), (uint32_t)wide_stages(ring));
+      walk_wide(w, S, pitch, 1 + rnd(5), (uint32_t)wide_stages(ring),
+                (uint32_t)wide_blocks_per_barrier(ring));
     }
   const Ring rings[] = {{4, 5, 0x1F, 0}, {8, 17, 0x139, 0}, {8, 17, 0x1D7, 0}, {10, 11, 0x7FF, 0},
                         {6, 9, 0x49, 0},  {4, 5, 0x1F, 1},   {10, 11, 0x7FF, 1}, {6, 9, 0x49, 1}};
