@@ -34,7 +34,7 @@ struct WideSrc {
   __device__ uint32_t pitch() const { return (uint32_t)a.w[1]; }
   __device__ uint32_t groups() const { return (uint32_t)(a.w[1] >> 32); }
   __device__ int nout() const { return (int)((a.w[2 + g / 16] >> (4 * (g % 16))) & 15u); }
-  // the input addresses (read up to k + D - 2 words on: output pointers and
+  // the input addresses (read up to D + B words past the k-th: output pointers and
   // records, all inside the argument block)
   __device__ const PYRIT_AS4 uint64_t *in_words() const {
     return (const PYRIT_AS4 uint64_t *)&a.w[kH];

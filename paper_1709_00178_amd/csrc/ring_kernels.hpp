@@ -544,8 +544,9 @@ __device__ __forceinline__ void wait_vmcnt() {
 // nothing.
 //
 // Src supplies k(), S(), pitch(), nout(), out(r), in_words() (the k input
-// block addresses, wave-uniform, readable past k: those reads only address
-// loads with an empty descriptor), records() (this wave's coefficient
+// block addresses, wave-uniform, readable up to D + B words past k: those
+// reads only address loads with an empty descriptor, or go unused),
+// records() (this wave's coefficient
 // records, one per input block, readable one past the last; at most B - 1
 // blocks past the last are skipped), unpack(record)
 // -> Lift8 and kHi16 (see accumulate).  The per-block scalar work is kept
@@ -586,24 +587,34 @@ __device__ __forceinline__ void code_column_staged(const Src &src, uint32_t col,
     const bool live = q < kLoads;
     const uint32_t qq = live ? q : q % kLoads;
     soff[u] = (qq / V) * pitch + (qq % V) * 4u;
-    loff[u] = live ? q * 64u : D * kLoads * 64u;
+    loff[u] = (live ? q * 64u : D * kLoads * 64u) * 4u;  // bytes
     smask[u] = live ? 0xFFFFFFFFu : 0u;
+    // (held as plain scalar words, opaque to the compiler: otherwise it
+    // rebuilds the mask from `live` at every load, a compare-and-select of
+    // four scalar instructions instead of one AND)
+    smask[u] = __builtin_amdgcn_readfirstlane(smask[u]);
+    loff[u] = __builtin_amdgcn_readfirstlane(loff[u]);
+    __asm__ volatile("" : "+s"(smask[u]), "+s"(loff[u]));
   });
   const auto *ip = src.in_words();     // address of input block jj at ip[jj]
   const auto *rec = src.records();     // coefficient record of block j at rec[j]
   constexpr uint32_t kStage = kLoads * 64u;
-  auto issue = [&](int jj) {
+  auto issue = [&](int jj, const uint8_t *in) {
     const uint32_t bytes = jj < k ? span : 0u;
-    const uint8_t *in = (const uint8_t *)ip[jj];
-    const uint32_t slot = (uint32_t)(jj & (D - 1)) * kStage;
+    const uint32_t slot = (uint32_t)(jj & (D - 1)) * (kStage * 4u);  // bytes
     static_for<0, NG>([&](auto uc) {
       constexpr int u = decltype(uc)::value;
       const __amdgpu_buffer_rsrc_t r = block_rsrc(in, bytes);
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr)(stage + ((slot & smask[u]) + loff[u])),
-                                               4, voff, soff[u], 0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          r, (lds_ptr)((char *)stage + ((slot & smask[u]) + loff[u])), 4, voff, soff[u], 0, 0);
     });
   };
-  for (int jj = 0; jj < D - B; ++jj) issue(jj);
+  for (int jj = 0; jj < D - B; ++jj) issue(jj, (const uint8_t *)ip[jj]);
+  // the addresses of the blocks issued at the next step, read a step ahead
+  const uint8_t *pin[B];
+  static_for<0, B>([&](auto bc) {
+    pin[decltype(bc)::value] = (const uint8_t *)ip[D - B + decltype(bc)::value];
+  });
   Lift8 cf = src.unpack(rec[0]);
   for (int j = 0; j < k; j += B) {
     wait_vmcnt<(D - 2 * B) * NG>();
@@ -612,7 +623,11 @@ __device__ __forceinline__ void code_column_staged(const Src &src, uint32_t col,
     __asm__ volatile("" ::: "memory");
     __builtin_amdgcn_s_barrier();
     __asm__ volatile("" ::: "memory");
-    static_for<0, B>([&](auto bc) { issue(j + D - B + decltype(bc)::value); });
+    static_for<0, B>([&](auto bc) {
+      constexpr int b = decltype(bc)::value;
+      issue(j + D - B + b, pin[b]);
+      pin[b] = (const uint8_t *)ip[j + D + b];
+    });
     static_for<0, B>([&](auto bc) {
       constexpr int b = decltype(bc)::value;
       const int jb = j + b;
