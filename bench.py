@@ -526,7 +526,10 @@ def bench_paper_shapes(args, stream, out, log):
     S bytes at a pitch of S + 4 KiB) show the same kernels against the HBM
     roofline on the algorithmic bytes, (k + m) w S: every block read or
     written once.  `one_pass_per_group` times the same encode as one launch
-    per group of eight parity blocks, each re-reading the data."""
+    per group of eight parity blocks, each re-reading the data.
+    `traffic_over_algorithmic`: the wide launch's HBM bytes from the
+    committed counter runs (FETCH_SIZE, WRITE_SIZE) over the algorithmic
+    bytes, when the kernel sources are the ones those runs measured."""
     import torch
 
     import paper_1709_00178_amd as P
@@ -563,6 +566,9 @@ def bench_paper_shapes(args, stream, out, log):
                         r["GBps_moved"] = round(moved / (ms * 1e-3) / 1e9, 1)
                         r["frac_of_peak"] = round(moved / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
                         if groups > 1:
+                            hbm = traffic_record(f"wide_{k + m}_{k}_{tr}")
+                            if hbm is not None:
+                                r["traffic_over_algorithmic"] = round(hbm / moved, 4)
                             fp = lambda: plan.encode(bl[:k], bl[k:], st.S, stream=stream,
                                                      pitch=st.pitch, vec_bytes=4)
                             fp()

@@ -621,15 +621,17 @@ def test_wide_passes_encode_and_decode(w, n, p, k, m, transform):
 # column chunk (G output groups per launch, as many as the kernel arguments
 # hold).  Each case against the oracle, whole blocks, ragged S over several
 # workgroups, and against the one-pass-per-group path (vec_bytes = 4).
-# Cases: three uneven groups in one launch on every ring and transform; the
-# paper's (60,40) and (60,20) shapes; codes whose outputs need several wide
-# launches (k = 64).
+# Cases: three uneven groups in one launch on every ring and transform (odd k
+# on the rings coding two blocks per barrier, so the last step holds one);
+# the paper's (60,40) and (60,20) shapes; codes whose outputs need several
+# wide launches (k = 64).
 @pytest.mark.parametrize("w,n,p,k,m,transform", [
     (4, 5, 0x1F, 5, 11, "embedding"), (4, 5, 0x1F, 3, 13, "parity"),
     (8, 17, 0x139, 9, 11, "embedding"), (8, 17, 0x1D7, 7, 9, "embedding"),
     (10, 11, 0x7FF, 12, 13, "embedding"), (10, 11, 0x7FF, 11, 17, "parity"),
     (6, 9, 0x49, 40, 20, "embedding"), (6, 9, 0x49, 20, 40, "parity"),
-    (6, 9, 0x49, 20, 40, "embedding"), (10, 11, 0x7FF, 64, 40, "embedding"),
+    (6, 9, 0x49, 20, 40, "embedding"), (6, 9, 0x49, 7, 12, "embedding"),
+    (6, 9, 0x49, 9, 11, "parity"), (10, 11, 0x7FF, 64, 40, "embedding"),
     (8, 17, 0x139, 64, 14, "embedding")])
 def test_wide_launches_match_oracle_and_passes(w, n, p, k, m, transform):
     torch = torch_mod()
