@@ -710,7 +710,11 @@ def bench_c3(args, stream, out, log):
 def bench_c4(args, stream, out, log):
     """Served mix: Poisson arrivals at 20k/s for 2 s of requests from the
     uneven distribution plus 5% k=10 m=4 GF(2^8) requests of 64 MiB blocks;
-    64 GiB output pool; continuous batching against one request per launch."""
+    64 GiB output pool; continuous batching against one request per launch.
+    At 20k/s, after one untimed pass, the two forms run three times each,
+    alternating, and each reports its run of median p99 (`p99_ms_runs`: all
+    three), since the p99 of one 2 s run moves by several percent from run
+    to run."""
     import torch
 
     from paper_1709_00178_amd import serve
@@ -726,14 +730,32 @@ def bench_c4(args, stream, out, log):
         res = {"rate_per_s": rate, "duration_s": dur, "requests": len(trace),
                "offered_GBps_data": round(offered / 1e9, 1), "prepare_s": round(prep_s, 2),
                "pool_GiB": 64, "slots": 4}
-        for name, per_req in [("batched", False), ("per_request_plain", True)]:
-            sv = serve.Server(pool_bytes=64 << 30, slots=4, per_request=per_req,
-                              release_outputs=True, block_skew=BLOCK_SKEW)
-            r, st = sv.run(prep.array)
-            res[name] = serve.summarize(prep, r, st)
-            log(f"{key} {name}: {res[name]}")
+        reps = 3 if key == "c4" else 1
+        if key == "c4":
+            # one untimed pass first: the first launch of each kernel variant
+            # the mix uses loads its code, which would land in whichever form
+            # ran first
+            sv = serve.Server(pool_bytes=64 << 30, slots=4, release_outputs=True,
+                              block_skew=BLOCK_SKEW)
+            sv.run(prep.array)
             sv.close()
             torch.cuda.empty_cache()
+        runs = {"batched": [], "per_request_plain": []}
+        for _ in range(reps):
+            for name, per_req in [("batched", False), ("per_request_plain", True)]:
+                sv = serve.Server(pool_bytes=64 << 30, slots=4, per_request=per_req,
+                                  release_outputs=True, block_skew=BLOCK_SKEW)
+                r, st = sv.run(prep.array)
+                runs[name].append(serve.summarize(prep, r, st))
+                log(f"{key} {name}: {runs[name][-1]}")
+                sv.close()
+                torch.cuda.empty_cache()
+        for name, rs in runs.items():
+            med = sorted(rs, key=lambda x: x["p99_ms"])[len(rs) // 2]
+            res[name] = dict(med)
+            if reps > 1:
+                res[name]["p99_ms_runs"] = [x["p99_ms"] for x in rs]
+                res[name]["p99_ms_small_runs"] = [x["p99_ms_small"] for x in rs]
         out[key] = res
     del inputs
     torch.cuda.empty_cache()

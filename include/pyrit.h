@@ -439,9 +439,11 @@ int pyrit_batch_run_noalloc(const pyrit_batch_item *items, int n_items, const py
  * kernels above), so requests arriving while earlier ones run are coded in
  * overlapping launches.  Plans and input buffers stay resident; the server
  * owns the output pool, the per-slot descriptor buffers and the streams.
- * A launch that carries at most four requests runs the plain kernel once per
- * request, back to back on its stream (arguments in the kernel-argument
- * segment, nothing uploaded first); larger ones run one batch kernel.
+ * Queued small requests that the idle slots can hold go out one per slot;
+ * beyond that they go out together on one slot.  A launch that carries at
+ * most four requests runs the plain kernel once per request, back to back
+ * on its stream (arguments in the kernel-argument segment, nothing uploaded
+ * first); larger ones run one batch kernel.
  */
 typedef struct {
   double arrival_s;             /* seconds after the start of the run */

@@ -267,7 +267,9 @@ int pyrit_server_run(pyrit_server *sv, const pyrit_request *reqs, int n, pyrit_r
       }
       // Launch on free slots.  A large request (moving at least large_bytes)
       // goes out alone, on at most slots-1 slots so that one slot stays for
-      // small requests; all admitted small requests go out together.
+      // small requests.  Admitted small requests that the idle slots can hold
+      // go out one per slot, running side by side on their streams; more than
+      // that go out together on one slot.
       for (auto &sl : sv->slots) {
         if (admitted.empty() && admitted_large.empty()) break;
         if (sl.busy) continue;
@@ -283,7 +285,9 @@ int pyrit_server_run(pyrit_server *sv, const pyrit_request *reqs, int n, pyrit_r
         } else {
           src = &admitted;
           take = (int)admitted.size();
-          if (cfg.per_request) take = 1;
+          int idle = 0;  // this slot and the other idle ones
+          for (auto &o : sv->slots) idle += !o.busy;
+          if (cfg.per_request || take <= idle) take = 1;
           else if (max_batch) take = std::min(take, max_batch);
         }
         ids.assign(src->begin(), src->begin() + take);
