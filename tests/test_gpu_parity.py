@@ -585,12 +585,14 @@ def test_parity_transform_decode(w, n, p):
 
 
 # Passes of up to ring_max_out outputs: 8 for n <= 9, 6 for n = 11, 4 for
-# n = 17; m above the limit splits into several passes.
+# n = 17; m above the limit splits into several passes (or wide launches),
+# for the encode and for a decode of m erasures (the paper's (60,40) shape
+# among them).
 @pytest.mark.parametrize("w,n,p,k,m,transform", [
     (4, 5, 0x1F, 8, 8, "embedding"), (4, 5, 0x1F, 7, 9, "parity"),
     (6, 9, 0x49, 10, 8, "embedding"), (6, 9, 0x49, 11, 17, "parity"),
     (10, 11, 0x7FF, 10, 6, "embedding"), (10, 11, 0x7FF, 9, 7, "parity"),
-    (8, 17, 0x1D7, 6, 5, "embedding")])
+    (8, 17, 0x1D7, 6, 5, "embedding"), (6, 9, 0x49, 40, 20, "embedding")])
 def test_wide_passes_encode_and_decode(w, n, p, k, m, transform):
     torch = torch_mod()
     st = W.Stripe(w, n, p, k=k, m=m, B=64 * 200 * w, stripe=m, seed=41)
