@@ -646,6 +646,10 @@ __device__ __forceinline__ void code_column_staged(const Src &src, uint32_t col,
       cf = src.unpack(next);
     });
   }
+  // The loads issued past the last block (empty descriptors) still write
+  // their LDS slots: let them land before the wave can end and the
+  // workgroup's LDS pass to another workgroup.
+  wait_vmcnt<0>();
   if (col >= S) return;
 #pragma unroll
   for (int r = 0; r < MO; ++r) {
